@@ -1,0 +1,93 @@
+"""Closed-form value iteration of the linear-quadratic game (test pin).
+
+The game of Section 2 is linear-quadratic: the drift is affine in (p, u) and
+the instant payoff is quadratic.  If every V_i^{[r]} is a quadratic
+    V_i(p) = 1/2 p^T Q_i p + q_i^T p + s_i
+and every control is affine, u_l(p) = a_l + f_l^T p, then one Bellman
+iteration of Section 2.1 maps them to a quadratic/affine pair again, as long
+as the maximiser lies inside the admissible interval.  With at least 3
+Chebyshev nodes per dimension the interpolant of a quadratic is the quadratic
+itself (also outside the box), and with at least 3 control nodes the fit in
+u of a quadratic is exact, so the Chebyshev iteration must reproduce this
+recursion at the nodes up to rounding.
+
+Derivation, player i, other players frozen at their affine controls:
+    y(u) = E p + e0 + b u,   E = I + h M + h sum_{l != i} beta_l e_l f_l^T,
+    e0 = h sum_{l != i} beta_l a_l e_l,   b = h beta_i e_i,   M = diag(1/m) K - diag(c)
+    d/du [h G_i + delta V_i(y(u))] = 0
+    => u* = [h A_i + delta b^T (Q_i (E p + e0) + q_i)] / (h - delta b^T Q_i b)
+Substituting u* back gives the new (Q_i, q_i, s_i).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+class LQState:
+    def __init__(self, d: int):
+        self.Q = np.zeros((d, d, d))
+        self.q = np.zeros((d, d))
+        self.s = np.zeros(d)
+        self.a = np.zeros(d)
+        self.f = np.zeros((d, d))
+
+    def value(self, i: int, P: np.ndarray) -> np.ndarray:
+        """V_i at the rows of P (n x d)."""
+        return 0.5 * np.einsum("nj,jk,nk->n", P, self.Q[i], P) + P @ self.q[i] + self.s[i]
+
+    def control(self, i: int, P: np.ndarray) -> np.ndarray:
+        return self.a[i] + P @ self.f[i]
+
+
+def lq_iterate(game, steps: int):
+    """Yield the LQState after each of ``steps`` iterations from V = 0, u = A."""
+    d = game.d
+    K = np.asarray(game.K, dtype=np.float64)
+    m = np.asarray(game.m, dtype=np.float64)
+    M = K / m[:, None] - np.diag(game.c)
+    h, delta = game.h, 1.0 - game.rho * game.h
+    I = np.eye(d)
+    st = LQState(d)
+    st.a = np.asarray(game.A, dtype=np.float64).copy()
+    for _ in range(steps):
+        nx = LQState(d)
+        for i in range(d):
+            E = I + h * M
+            e0 = np.zeros(d)
+            for l in range(d):
+                if l != i:
+                    E = E + h * game.beta[l] * np.outer(I[l], st.f[l])
+                    e0 = e0 + h * game.beta[l] * st.a[l] * I[l]
+            b = h * game.beta[i] * I[i]
+            Qi, qi, si = st.Q[i], st.q[i], st.s[i]
+            den = h - delta * b @ Qi @ b
+            fi = delta * (E.T @ Qi @ b) / den
+            ai = (h * game.A[i] + delta * b @ (Qi @ e0 + qi)) / den
+            F = E + np.outer(b, fi)
+            gv = e0 + b * ai
+            nx.Q[i] = h * (-np.outer(fi, fi) - game.phi[i] * np.outer(I[i], I[i])) + delta * F.T @ Qi @ F
+            nx.q[i] = h * (game.A[i] - ai) * fi + delta * (F.T @ Qi @ gv + F.T @ qi)
+            nx.s[i] = h * (game.A[i] * ai - 0.5 * ai * ai) + delta * (0.5 * gv @ Qi @ gv + qi @ gv + si)
+            nx.a[i], nx.f[i] = ai, fi
+        st = nx
+        yield st
+
+
+def node_points(game) -> np.ndarray:
+    """Physical node coordinates (N^d x d), C order, index 0 = p_max."""
+    n = game.N - 1
+    x = np.cos(np.pi * np.arange(game.N) / n)
+    p1 = 0.5 * game.p_max * (x + 1.0)
+    grids = np.meshgrid(*([p1] * game.d), indexing="ij")
+    return np.stack([g.ravel() for g in grids], axis=1)
+
+
+def lq_nodal(game, steps: int):
+    """(V, U) at the nodes after ``steps`` iterations, each (d, N^d)."""
+    P = node_points(game)
+    st = None
+    for st in lq_iterate(game, steps):
+        pass
+    V = np.stack([st.value(i, P) for i in range(game.d)])
+    U = np.stack([st.control(i, P) for i in range(game.d)])
+    return V, U

@@ -1,0 +1,196 @@
+"""Seeded synthetic inputs for the transboundary-pollution game solver.
+
+Both the CPU oracle tests and the GPU path draw their inputs from here. The
+module holds random-number generation and the assembly of game parameters
+from the nominal values printed in the paper's numerical section; it holds
+none of the method's arithmetic (no Chebyshev nodes, transforms, series
+evaluation or value iteration).
+
+Random numbers come from SplitMix64 (Steele, Lea & Flood, "Fast splittable
+pseudorandom number generators", OOPSLA 2014) used as a counter-based
+generator: ``uniform(seed, stream, i)`` hashes the triple, so any element of
+any stream can be drawn independently and in any order.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Optional
+
+import numpy as np
+
+_GOLDEN = np.uint64(0x9E3779B97F4A7C15)
+_M1 = np.uint64(0xBF58476D1CE4E5B9)
+_M2 = np.uint64(0x94D049BB133111EB)
+
+
+def splitmix64(x) -> np.ndarray:
+    """SplitMix64 finaliser applied to ``x + golden`` (vectorised, uint64 wrap)."""
+    with np.errstate(over="ignore"):
+        z = np.asarray(x, dtype=np.uint64) + _GOLDEN
+        z = (z ^ (z >> np.uint64(30))) * _M1
+        z = (z ^ (z >> np.uint64(27))) * _M2
+        return z ^ (z >> np.uint64(31))
+
+
+def uniform(seed: int, stream: int, idx) -> np.ndarray:
+    """Uniform doubles in [0, 1): top 53 bits of SplitMix64(key(seed, stream) ^ idx)."""
+    key = splitmix64(np.uint64(seed)) ^ (np.uint64(stream) << np.uint64(40))
+    z = splitmix64(key ^ np.asarray(idx, dtype=np.uint64))
+    return (z >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
+
+
+def normal(seed: int, stream: int, count: int) -> np.ndarray:
+    """Standard normal draws by Box-Muller from pairs (2i, 2i+1) of ``uniform``."""
+    i = np.arange(count, dtype=np.uint64)
+    u1 = uniform(seed, stream, 2 * i)
+    u2 = uniform(seed, stream, 2 * i + np.uint64(1))
+    u1 = 1.0 - u1  # (0, 1]: log is finite
+    return np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * np.pi * u2)
+
+
+# Nominal parameters of the paper's 2-player example (Section 4.1): beta_i = 1,
+# phi_i = 1, A_i = 0.5, c_i = 0.5; the exchange coefficient scale kappa = 1 is
+# the magnitude of the printed K entries.  The paper gives no value for the
+# discount rate rho; 0.1 is this project's nominal choice.
+NOMINAL = {"A": 0.5, "beta": 1.0, "phi": 1.0, "c": 0.5, "kappa": 1.0, "rho": 0.1}
+THETA_ORDER = ("A", "beta", "phi", "c", "kappa", "rho")
+
+# Exchange matrices of the paper's examples (Section 4): two players sharing a
+# border; three players in a chain; four players.  The printed 3-player matrix
+# has row 2 = [1, -2, 0], which contradicts the text (player 2 borders players
+# 1 and 3) and the zero row sums of the other two examples; the chain matrix
+# below restores the (2,3) entry to 1.
+K_EXAMPLES = {
+    1: [[0.0]],
+    2: [[-1.0, 1.0], [1.0, -1.0]],
+    3: [[-1.0, 1.0, 0.0], [1.0, -2.0, 1.0], [0.0, 1.0, -1.0]],
+    4: [[-1.0, 1.0, 0.0, 0.0], [1.0, -3.0, 1.0, 1.0],
+        [0.0, 1.0, -2.0, 1.0], [0.0, 1.0, 1.0, -2.0]],
+}
+
+
+@dataclass
+class Game:
+    """One game instance: the discrete-space LQ pollution game on a Chebyshev grid.
+
+    ``K`` is the d-by-d exchange matrix in the graph-Laplacian convention
+    (off-diagonal entries >= 0, diagonal = minus the row's exchange), so the
+    drift is g(p, u) = K p / m - c p + beta u.
+    """
+    d: int
+    N: int                      # Chebyshev-Lobatto nodes per state dimension
+    h: float
+    rho: float
+    p_max: float
+    u_max: float
+    K: np.ndarray               # (d, d)
+    m: np.ndarray               # (d,)
+    c: np.ndarray
+    beta: np.ndarray
+    A: np.ndarray
+    phi: np.ndarray
+    Nu: int = 0                 # control nodes per player; 0 means N
+    theta: Optional[np.ndarray] = field(default=None)  # the 6 scalars drawn, if shared
+
+    @property
+    def n_u(self) -> int:
+        return self.Nu if self.Nu > 0 else self.N
+
+    @property
+    def n_nodes(self) -> int:
+        return self.N ** self.d
+
+
+def draw_theta(seed: int, instance: int) -> np.ndarray:
+    """theta = nominal * (0.5 + U[0,1)) for (A, beta, phi, c, kappa, rho)."""
+    q = np.arange(6, dtype=np.uint64)
+    u = uniform(seed, 1 + instance, q)
+    nom = np.array([NOMINAL[k] for k in THETA_ORDER])
+    return nom * (0.5 + u)
+
+
+def make_game(d: int, N: int, seed: int, instance: int = 0, *, h: float = 1e-2,
+              p_max: float = 1.0, u_max: float = 1.0, Nu: int = 0,
+              per_player: bool = False, nominal: bool = False) -> Game:
+    """A seeded game shaped like the paper's examples.
+
+    Default: the six scalars of ``draw_theta`` shared by all players, with
+    K = kappa * K_example[d].  ``per_player=True`` draws A, beta, phi, c
+    separately for every player and perturbs each edge weight of K (keeping
+    it symmetric with zero row sums), so that player and mode indices can no
+    longer be swapped without changing the answer.  ``nominal=True`` uses the
+    nominal parameters exactly.
+    """
+    Kd = np.array(K_EXAMPLES[d], dtype=np.float64)
+    if nominal:
+        th = np.array([NOMINAL[k] for k in THETA_ORDER])
+    else:
+        th = draw_theta(seed, instance)
+    A, beta, phi, c, kappa, rho = th
+    ones = np.ones(d)
+    if per_player:
+        base = 1000 + instance
+        draws = uniform(seed, base, np.arange(4 * d + d * d, dtype=np.uint64))
+        A_v = NOMINAL["A"] * (0.5 + draws[0:d])
+        beta_v = NOMINAL["beta"] * (0.5 + draws[d:2 * d])
+        phi_v = NOMINAL["phi"] * (0.5 + draws[2 * d:3 * d])
+        c_v = NOMINAL["c"] * (0.5 + draws[3 * d:4 * d])
+        w = draws[4 * d:].reshape(d, d)
+        K = np.zeros((d, d))
+        for i in range(d):
+            for j in range(i + 1, d):
+                if Kd[i, j] != 0.0:
+                    K[i, j] = K[j, i] = kappa * Kd[i, j] * (0.5 + w[i, j])
+        K -= np.diag(K.sum(axis=1))
+        return Game(d, N, h, rho, p_max, u_max, K, ones.copy(), c_v, beta_v, A_v, phi_v, Nu, None)
+    return Game(d, N, h, rho, p_max, u_max, kappa * Kd, ones.copy(), c * ones, beta * ones,
+                A * ones, phi * ones, Nu, th.copy())
+
+
+def random_state(game: Game, seed: int, stream: int = 77, scale: float = 1.0):
+    """Seeded nodal state (V, U), each of shape (d, N**d), C order over nodes.
+
+    V is white noise in [-scale, 0]; U is uniform in [0, u_max].  Used for
+    one-step comparisons from states that are not the zero start.
+    """
+    n = game.d * game.n_nodes
+    V = -scale * uniform(seed, stream, np.arange(n, dtype=np.uint64))
+    U = game.u_max * uniform(seed, stream + 1, np.arange(n, dtype=np.uint64))
+    return V.reshape(game.d, game.n_nodes), U.reshape(game.d, game.n_nodes)
+
+
+def coef_tensor(d: int, N: int, seed: int, decay: float = 0.3) -> np.ndarray:
+    """c_k = N(0,1) * exp(-decay * sum(k)), shape (N,)*d, FP64 (stream 0)."""
+    g = normal(seed, 0, N ** d).reshape((N,) * d)
+    ks = np.indices((N,) * d).sum(axis=0)
+    return g * np.exp(-decay * ks)
+
+
+def query_points(d: int, npts: int, seed: int, lo: float = -1.0, hi: float = 1.0) -> np.ndarray:
+    """npts points uniform in [lo, hi]^d, shape (npts, d), FP64 (stream 1)."""
+    u = uniform(seed, 1 << 20, np.arange(npts * d, dtype=np.uint64))
+    return (lo + (hi - lo) * u).reshape(npts, d)
+
+
+# Workloads of the benchmark configurations (seeds 1..5 in order).
+def config_game(name: str, instance: int = 0) -> Game:
+    if name == "C1":
+        return make_game(2, 16, seed=1, instance=instance)
+    if name == "C2":
+        return make_game(3, 32, seed=2, instance=instance)
+    if name == "C3":
+        return make_game(4, 24, seed=3, instance=instance)
+    if name == "C5":
+        return make_game(3, 24, seed=5, instance=instance)
+    raise KeyError(name)
+
+
+def batch_games(count: int = 256, seed: int = 4):
+    """Ragged batch: d ~ U{2,3}, N ~ U{12,16,24,32}, theta per instance."""
+    out = []
+    for inst in range(count):
+        u = uniform(seed, 5000 + inst, np.arange(2, dtype=np.uint64))
+        d = 2 + int(u[0] * 2)
+        N = (12, 16, 24, 32)[int(u[1] * 4)]
+        out.append(make_game(d, N, seed=seed, instance=inst))
+    return out
