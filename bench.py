@@ -1,0 +1,136 @@
+#!/usr/bin/env python3
+"""Throughput of the tensorial Chebyshev value iteration on one MI355X.
+
+Workload: the d=3 player game on N=32 Lobatto nodes per dimension (32768
+state nodes), seeded parameters (seed 2), zero terminal value, 200
+value-iteration steps = one "solve".  A bench step is one whole solve (all
+kernels of every iteration: coefficient transform, contraction, line fit,
+argmax, residual).  Prints one JSON line.
+
+  python bench.py [--steps K] [--warmup W] [--precision fp64|fp32corr]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "game solves/s and node-evals/s at d=3,N=32, err≤1e-8 vs FP64; mixed vs FP64 GPU"
+TIME_STEPS = 200
+PEAK = {"fp64": 78.6, "fp32": 157.3}       # TFLOP/s, MI355X dense MFMA
+HBM_PEAK = 8000.0                           # GB/s
+
+
+def cpu_baseline(g, steps: int):
+    """The oracle's solve rate on this host, from `steps` full iterations."""
+    import oracle
+    V, U = oracle.zero_state(g)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        V, U, _, _ = oracle.step(g, V, U)
+    dt = time.perf_counter() - t0
+    per_solve = dt / steps * TIME_STEPS
+    return {"value": 1.0 / per_solve, "unit": "solves/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{steps} full value-iteration steps of the same d=3,N=32 game from the zero terminal "
+                      f"value ({dt:.1f} s), scaled to {TIME_STEPS} steps"}
+
+
+def err_vs_reference(G, g):
+    """Max |V - V_oracle| / max|V_oracle| on the sampled nodes of the committed
+    200-step oracle reference (tests/golden/c2_oracle_reference.json)."""
+    import numpy as np
+    path = os.path.join(ROOT, "tests", "golden", "c2_oracle_reference.json")
+    if not os.path.exists(path):
+        return None
+    ref = json.load(open(path))
+    snap = ref["snapshots"].get(str(TIME_STEPS))
+    if snap is None:
+        return None
+    V, U, _ = G.get_state()
+    V = V.cpu().numpy()
+    pl, nd = np.array(ref["players"]), np.array(ref["nodes"])
+    e = np.max(np.abs(V[pl, nd] - np.array(snap["V"]))) / ref["vmax"][TIME_STEPS - 1]
+    return {"max_rel_V": float(e), "points": int(len(pl)), "step": TIME_STEPS,
+            "source": "oracle reference at 512 sampled (player, node) pairs"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5, help="timed solves")
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32corr"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=2, help="oracle iterations timed for the CPU baseline")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (for scaling rocprof byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (instances or node blocks "
+              "would shard across GPUs with no or one all-gather per step; not built).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import workloads as W
+    from paper_2307_04688_amd import chebgame as cg
+
+    torch.cuda.set_device(0)
+    g = W.config_game("C2")
+    prec = cg.FP64 if args.precision == "fp64" else cg.FP32_CORR
+    print(f"bench: d={g.d} N={g.N} steps={TIME_STEPS} precision={args.precision}", file=sys.stderr, flush=True)
+    G = cg.ChebGame(g, prec)
+    for _ in range(args.warmup):
+        G.reset()
+        G.solve(TIME_STEPS)
+    torch.cuda.synchronize()
+    G.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        G.reset()
+        G.solve(TIME_STEPS)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kernel_ms, launches = G.profile(False)
+    ms_per_solve = (t1 - t0) * 1e3 / max(args.steps, 1)
+    solves_per_s = 1e3 / ms_per_solve
+    NN = g.N ** g.d
+    node_evals = solves_per_s * TIME_STEPS * g.d * NN
+
+    # roofline of the dominant kernel (fused contraction step): algorithmic
+    # contraction flops per launch = d players * 2 N^(2d)
+    flops_launch = g.d * 2.0 * float(g.N) ** (2 * g.d)
+    avg_ms = kernel_ms / max(launches, 1)
+    achieved = flops_launch / (avg_ms * 1e-3) / 1e12
+    peak = PEAK["fp64"] if prec == cg.FP64 else PEAK["fp32"]
+    roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+            "traffic": None, "kernel": "k_step_f64" if prec == cg.FP64 else "k_step_mixed",
+            "avg_launch_ms": avg_ms, "launches": launches, "flops_per_launch": flops_launch}
+
+    err = err_vs_reference(G, g)
+
+    if args.copy_calibration:
+        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+
+    out = {"metric": METRIC, "value": solves_per_s, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms_per_solve, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64" if prec == cg.FP64 else "f32+f64", "data": "synthetic",
+           "config": {"workload": "LQ pollution game d=3 players, N=32 nodes/dim (32768 nodes), 200 value-"
+                                  "iteration steps from zero terminal value, seed-2 parameters",
+                      "d": g.d, "N": g.N, "time_steps": TIME_STEPS, "precision": args.precision},
+           "node_evals_per_s": node_evals, "roofline": roof, "err_vs_oracle": err}
+    if not args.no_cpu_baseline:
+        print("bench: timing the CPU oracle", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(g, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,175 @@
+/*
+ * chebgame.h -- C ABI of libchebgame.so, a gfx950 (MI355X) implementation of
+ * the tensorial Chebyshev value iteration for the J-player transboundary
+ * pollution game of de Castro, Gaton & Gomez (arXiv 2307.04688).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Every function returns an int status: CG_OK (0) on success, a negative
+ *    CG_E* code on error, or the positive warning CG_ENOTCONVERGED.  On error
+ *    nothing observable has been written unless stated, and cg_last_error()
+ *    returns a message for the calling thread.  No C++ exception crosses the
+ *    ABI.
+ *  - Device pointers ("_dev") are addresses in the memory of the current HIP
+ *    device; they are owned by the caller and must stay valid until the work
+ *    queued on 'stream' has finished.  Host pointers are read during the
+ *    call only.  'stream' is a hipStream_t passed as void* (NULL = the null
+ *    stream).  Work is queued asynchronously on it unless a function says it
+ *    synchronises.
+ *  - Tensors are FP64, C order (last mode fastest).  A value tensor of shape
+ *    N x ... x N holds the values at the Chebyshev-Lobatto nodes
+ *    x_k = cos(pi k / (N-1)), k = 0..N-1, so index 0 is x = +1 (Section 3.1);
+ *    a coefficient tensor holds c_k of sum_k c_k T_{k_1}(x_1)...T_{k_d}(x_d).
+ *  - State arrays of a game are [d][N^d]: player-major, then node index in
+ *    C order.  State coordinates are physical, p in [0, p_max]^d, mapped to
+ *    [-1,1]^d by x = 2 p / p_max - 1 (Section 3.4).
+ */
+#ifndef CHEBGAME_H
+#define CHEBGAME_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+#define CG_OK 0
+#define CG_ENOTCONVERGED 1   /* warning: max_steps reached before the tolerance */
+#define CG_EINVAL (-1)       /* invalid argument (message says which) */
+#define CG_EUNSUPPORTED (-2) /* size or precision outside the compiled set */
+#define CG_EDEVICE (-3)      /* HIP runtime error or no gfx950 device */
+#define CG_ENOMEM (-4)       /* workspace too small */
+#define CG_ENONFINITE (-5)   /* a non-finite value appeared in the iterate */
+
+/* Arithmetic of the contractions.  CG_FP64: everything in binary64 (MFMA
+ * f64).  CG_FP32 / CG_BF16 (cg_chebyshev_eval only): basis and coefficients
+ * rounded to binary32 / bfloat16, products accumulated in binary32 on MFMA.
+ * CG_FP32_CORR (games only): the contraction is split into an FP64 part
+ * (value and first-order Taylor term at the node, computed by small mode
+ * products) and a second-order remainder contracted on binary32 MFMA; the
+ * transform, line fit, argmax, step accumulation and residual stay FP64. */
+#define CG_FP64 0
+#define CG_FP32 1
+#define CG_BF16 2
+#define CG_FP32_CORR 3
+
+/* Sizes compiled into the library. */
+#define CG_MAX_D 4   /* players (state dimension) */
+#define CG_MAX_N 32  /* nodes per dimension */
+
+/* Game description: the discrete-space LQ game of Section 2 with the time
+ * discretisation of Section 2.1 and the grids of Section 3.4.
+ *   drift      g_i(p,u) = (K p)_i / m_i - c_i p_i + beta_i u_i
+ *              (K in the graph-Laplacian convention of the paper's examples:
+ *              off-diagonal k_ij >= 0, diagonal = -(exchange + leakage))
+ *   payoff     G_i(p,u) = u_i (A_i - u_i / 2) - phi_i p_i^2 / 2
+ *   Bellman    V_i(p) = max_{0 <= u <= u_max} { h G_i(p_i,u)
+ *                       + (1 - rho h) V_i(p + h g(p, [u, u_{-i}])) }
+ * All host arrays are copied by cg_init_game. */
+typedef struct cg_game_desc {
+    int32_t d;          /* players = state dimension, 2..CG_MAX_D */
+    int32_t n_nodes;    /* N: Lobatto nodes per state dimension, 3..CG_MAX_N */
+    int32_t n_unodes;   /* control nodes per player on [0,u_max], 3..CG_MAX_N; 0 = N */
+    int32_t reserved;   /* must be 0 */
+    double h;           /* time step, > 0 */
+    double rho;         /* discount rate; requires 0 < rho h < 1 */
+    double p_max;       /* state box [0, p_max]^d, > 0 */
+    double u_max;       /* control interval [0, u_max], > 0 */
+    const double *K;    /* d*d row-major exchange matrix */
+    const double *m;    /* d region measures (NULL = all 1), > 0 */
+    const double *c;    /* d decay rates */
+    const double *beta; /* d emission-to-stock factors */
+    const double *A;    /* d benefit coefficients */
+    const double *phi;  /* d damage coefficients */
+} cg_game_desc;
+
+typedef struct cg_game cg_game;
+
+/* Message for the last failing call on this thread ("" if none). */
+const char *cg_last_error(void);
+/* Static description of a status code. */
+const char *cg_strerror(int status);
+
+/* Bytes of device workspace cg_init_game needs for this game and precision
+ * (0 if the description is invalid; cg_last_error says why). */
+size_t cg_workspace_bytes(const cg_game_desc *desc, int precision);
+
+/* Step 0 of Section 2.1 (offline set-up).  Validates the description, builds
+ * the node and control grids (Section 3.4) and the constants, carves the
+ * caller-owned workspace ws_dev (>= cg_workspace_bytes, 256-byte aligned)
+ * and queues on 'stream' the start V^{[0]} = 0 (zero terminal value),
+ * u^{[0]} = A.  *out receives a handle that owns no device memory; the
+ * workspace must outlive it.  precision: CG_FP64 or CG_FP32_CORR.
+ * Errors: CG_EINVAL (bad description), CG_EUNSUPPORTED (d or N outside the
+ * compiled set), CG_ENOMEM (workspace too small), CG_EDEVICE. */
+int cg_init_game(const cg_game_desc *desc, int precision, void *ws_dev, size_t ws_bytes,
+                 void *stream, cg_game **out);
+
+/* Releases the handle (not the workspace).  NULL is accepted. */
+int cg_destroy(cg_game *game);
+
+/* Algorithm Cnv (Section 3.1, eq. (forcoef) along every mode): coefficient
+ * tensors of 'batch' value tensors of shape n[0] x ... x n[d-1], stored one
+ * after the other in vals_dev; coef_dev receives them in the same layout and
+ * must not overlap vals_dev.  1 <= d <= CG_MAX_D, 2 <= n[l] <= CG_MAX_N.
+ * Queued on 'stream'.  Errors: CG_EINVAL, CG_EUNSUPPORTED, CG_EDEVICE. */
+int cg_chebyshev_transform(int d, const int32_t *n, const double *vals_dev, double *coef_dev,
+                           int64_t batch, void *stream);
+
+/* Value of the series sum_k c_k T_{k_1}(x_1)...T_{k_d}(x_d) (Definition of
+ * the n-dimensional interpolant, Section 3.1; evaluation by mode products as
+ * in Section 3.2) at npts points.  coef_dev: shape n[0] x ... x n[d-1] FP64;
+ * x_dev: npts x d FP64 row-major, normalised coordinates (points outside
+ * [-1,1]^d are evaluated by polynomial continuation); out_dev: npts values,
+ * double for CG_FP64, float for CG_FP32 and CG_BF16.  1 <= d <= CG_MAX_D,
+ * 2 <= n[l] <= CG_MAX_N.  Needs cg_eval_workspace_bytes() bytes of device
+ * workspace in ws_dev.  Queued on 'stream'. */
+size_t cg_eval_workspace_bytes(int d, const int32_t *n, int precision);
+int cg_chebyshev_eval(int d, const int32_t *n, const double *coef_dev, const double *x_dev,
+                      int64_t npts, void *out_dev, int precision, void *ws_dev, size_t ws_bytes,
+                      void *stream);
+
+/* nsteps iterations r -> r+1 of Steps 1-4 (Section 2.1, implemented as in
+ * Section 3.4): coefficient transform of every V_i^{[r]}, evaluation of V_i at
+ * every node's update points p + h g(p, [u_m, u^{[r]}_{-i}(p)]) for the control
+ * nodes u_m, fit in u, argmax over [0, u_max], new value and control.  All
+ * players use the same u^{[r]} (simultaneous update).  If residual_out is not
+ * NULL the call synchronises 'stream' and stores max_{i,j} |V^{[r+1]} - V^{[r]}|
+ * of the last iteration there; otherwise it only queues the work.  Errors:
+ * CG_EINVAL, CG_EDEVICE, CG_ENONFINITE (only when synchronising). */
+int cg_step(cg_game *game, int32_t nsteps, double *residual_out);
+
+/* Iterates until the residual of an iteration is < tol (strict, the TOL test
+ * of Step 4, taken on the nodes) or max_steps iterations are done.  tol <= 0
+ * runs exactly max_steps iterations.  The test runs on the device: once an
+ * iteration meets it, later queued iterations leave the state unchanged, so
+ * the state is that of the first iteration below tol.  Synchronises 'stream'.
+ * *steps_done and *residual (either may be NULL) receive the iterations done
+ * by this call and the last residual.  Returns CG_ENOTCONVERGED if tol > 0 and
+ * it was not met. */
+int cg_solve(cg_game *game, int32_t max_steps, double tol, int32_t *steps_done, double *residual);
+
+/* Checkpoint / warm start.  cg_get_state copies the current V and U
+ * ([d][N^d] FP64 each, device) and stores the iteration count in *r (host,
+ * nullable); it queues the copies on the game's stream.  cg_set_state
+ * replaces them (U_dev NULL = u_i = A_i everywhere) and resets the
+ * convergence test; the iteration count is kept. */
+int cg_get_state(cg_game *game, double *V_dev, double *U_dev, int32_t *r);
+int cg_set_state(cg_game *game, const double *V_dev, const double *U_dev);
+
+/* Timing of the contraction kernel (the fused step kernel that carries the
+ * mode-n contractions).  With enable != 0, every later step records a pair of
+ * HIP events on the game's stream around that kernel's launch.  If kernel_ms
+ * or launches is not NULL the call first synchronises the stream and
+ * returns the summed elapsed time and the number of timed launches since the
+ * previous cg_profile call; the record is then cleared.  Costs one event
+ * pair per step while enabled. */
+int cg_profile(cg_game *game, int enable, double *kernel_ms, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CHEBGAME_H */

@@ -58,6 +58,7 @@ def lib() -> C.CDLL:
         if not os.path.exists(_LIB):
             build(force=True)
         L = C.CDLL(_LIB)
+        L.or_num_threads.restype = C.c_int
         L.or_nodes.argtypes = [C.c_int, _dp]
         L.or_cheb_T.argtypes = [C.c_int, C.c_double, _dp]
         L.or_coef_1d.argtypes = [C.c_int, _dp, C.c_long, _dp, C.c_long]
@@ -85,6 +86,11 @@ def _d(a: np.ndarray):
 
 def _f64(a) -> np.ndarray:
     return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def num_threads() -> int:
+    """OpenMP threads the oracle's parallel loops use."""
+    return int(lib().or_num_threads())
 
 
 def nodes(N: int) -> np.ndarray:

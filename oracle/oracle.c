@@ -18,11 +18,15 @@
  * node x_k = cos(pi k / (N-1)), so index 0 is x = +1.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
 
 #define OR_MAXD 4
 #define OR_MAXN 64
+
+/* Number of OpenMP threads the parallel loops below use. */
+int or_num_threads(void) { return omp_get_max_threads(); }
 
 /* cos(pi a / n) with a reduced modulo 2n first, so the argument stays in
  * [0, 2 pi).  Chebyshev nodes and T_l(alpha^k) = cos(pi l k / n) (Section

@@ -1,0 +1,246 @@
+"""ctypes binding of libchebgame.so (include/chebgame.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels behind the C ABI.  PyTorch supplies device memory and the stream.
+There is no CPU fallback: without the built library or a gfx950 device every
+call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libchebgame.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "chebgame.h")
+
+OK, ENOTCONVERGED, EINVAL, EUNSUPPORTED, EDEVICE, ENOMEM, ENONFINITE = 0, 1, -1, -2, -3, -4, -5
+FP64, FP32, BF16, FP32_CORR = 0, 1, 2, 3
+MAX_D, MAX_N = 4, 32
+
+
+class ChebGameError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"chebgame error {code}: {msg}")
+        self.code = code
+
+
+class GameDesc(C.Structure):
+    _fields_ = [("d", C.c_int32), ("n_nodes", C.c_int32), ("n_unodes", C.c_int32), ("reserved", C.c_int32),
+                ("h", C.c_double), ("rho", C.c_double), ("p_max", C.c_double), ("u_max", C.c_double),
+                ("K", C.POINTER(C.c_double)), ("m", C.POINTER(C.c_double)), ("c", C.POINTER(C.c_double)),
+                ("beta", C.POINTER(C.c_double)), ("A", C.POINTER(C.c_double)), ("phi", C.POINTER(C.c_double))]
+
+
+_lib: Optional[C.CDLL] = None
+
+
+def exported_names() -> list:
+    """Function names declared in include/chebgame.h."""
+    src = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(cg_[a-z_0-9]+)\s*\(", src, re.M)))
+
+
+def lib() -> C.CDLL:
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ChebGameError(EDEVICE, f"{LIB_PATH} is not built (run __graft_entry__.build())")
+    L = C.CDLL(LIB_PATH)
+    vp, dp, ip = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int32)
+    L.cg_last_error.restype = C.c_char_p
+    L.cg_strerror.restype = C.c_char_p
+    L.cg_strerror.argtypes = [C.c_int]
+    L.cg_workspace_bytes.restype = C.c_size_t
+    L.cg_workspace_bytes.argtypes = [C.POINTER(GameDesc), C.c_int]
+    L.cg_init_game.argtypes = [C.POINTER(GameDesc), C.c_int, vp, C.c_size_t, vp, C.POINTER(vp)]
+    L.cg_destroy.argtypes = [vp]
+    L.cg_chebyshev_transform.argtypes = [C.c_int, ip, vp, vp, C.c_int64, vp]
+    L.cg_eval_workspace_bytes.restype = C.c_size_t
+    L.cg_eval_workspace_bytes.argtypes = [C.c_int, ip, C.c_int]
+    L.cg_chebyshev_eval.argtypes = [C.c_int, ip, vp, vp, C.c_int64, vp, C.c_int, vp, C.c_size_t, vp]
+    L.cg_step.argtypes = [vp, C.c_int32, dp]
+    L.cg_solve.argtypes = [vp, C.c_int32, C.c_double, ip, dp]
+    L.cg_get_state.argtypes = [vp, vp, vp, ip]
+    L.cg_set_state.argtypes = [vp, vp, vp]
+    L.cg_profile.argtypes = [vp, C.c_int, dp, C.POINTER(C.c_int64)]
+    _lib = L
+    return L
+
+
+def last_error() -> str:
+    return lib().cg_last_error().decode()
+
+
+def _check(rc: int) -> int:
+    if rc < 0:
+        raise ChebGameError(rc, last_error())
+    return rc
+
+
+def _stream(stream=None) -> int:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _desc(game, keep: list) -> GameDesc:
+    """cg_game_desc from a workloads.Game (or any object with the same fields)."""
+    def arr(x):
+        a = np.ascontiguousarray(np.asarray(x, dtype=np.float64).ravel())
+        keep.append(a)
+        return a.ctypes.data_as(C.POINTER(C.c_double))
+    D = GameDesc()
+    D.d, D.n_nodes = int(game.d), int(game.N)
+    D.n_unodes = int(getattr(game, "Nu", 0) or 0)
+    D.reserved = 0
+    D.h, D.rho, D.p_max, D.u_max = float(game.h), float(game.rho), float(game.p_max), float(game.u_max)
+    D.K, D.m, D.c = arr(game.K), arr(game.m), arr(game.c)
+    D.beta, D.A, D.phi = arr(game.beta), arr(game.A), arr(game.phi)
+    return D
+
+
+def workspace_bytes(game, precision: int = FP64) -> int:
+    keep: list = []
+    return int(lib().cg_workspace_bytes(C.byref(_desc(game, keep)), precision))
+
+
+class ChebGame:
+    """A game handle (cg_game*) plus the torch-owned workspace it lives in."""
+
+    def __init__(self, game, precision: int = FP64, stream=None):
+        import torch
+        keep: list = []
+        desc = _desc(game, keep)
+        L = lib()
+        nbytes = int(L.cg_workspace_bytes(C.byref(desc), precision))
+        if nbytes == 0:
+            raise ChebGameError(EINVAL, last_error())
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        self.stream = stream
+        self.d, self.N = int(game.d), int(game.N)
+        self.precision = precision
+        h = C.c_void_p()
+        _check(L.cg_init_game(C.byref(desc), precision, C.c_void_p(self.ws.data_ptr()), nbytes,
+                              C.c_void_p(_stream(stream)), C.byref(h)))
+        self.handle = h
+
+    def step(self, nsteps: int = 1, sync: bool = True) -> Optional[float]:
+        r = C.c_double()
+        _check(lib().cg_step(self.handle, nsteps, C.byref(r) if sync else None))
+        return r.value if sync else None
+
+    def solve(self, max_steps: int, tol: float = 0.0) -> Tuple[int, int, float]:
+        """Returns (status, steps_done, last residual)."""
+        n = C.c_int32()
+        r = C.c_double()
+        rc = _check(lib().cg_solve(self.handle, max_steps, float(tol), C.byref(n), C.byref(r)))
+        return rc, n.value, r.value
+
+    def get_state(self):
+        import torch
+        NN = self.N ** self.d
+        V = torch.empty((self.d, NN), dtype=torch.float64, device="cuda")
+        U = torch.empty_like(V)
+        r = C.c_int32()
+        _check(lib().cg_get_state(self.handle, C.c_void_p(V.data_ptr()), C.c_void_p(U.data_ptr()), C.byref(r)))
+        return V, U, r.value
+
+    def set_state(self, V, U=None):
+        import torch
+        NN = self.N ** self.d
+        V = V.to(device="cuda", dtype=torch.float64).contiguous().reshape(self.d, NN)
+        U = None if U is None else U.to(device="cuda", dtype=torch.float64).contiguous().reshape(self.d, NN)
+        self._pin = (V, U)  # keep alive until the queued copy has run
+        _check(lib().cg_set_state(self.handle, C.c_void_p(V.data_ptr()),
+                                  C.c_void_p(U.data_ptr()) if U is not None else None))
+
+    def profile(self, enable: bool = True) -> Tuple[float, int]:
+        """(summed ms, launches) of the contraction kernel since the last call; (re)arms timing."""
+        ms = C.c_double()
+        n = C.c_int64()
+        _check(lib().cg_profile(self.handle, 1 if enable else 0, C.byref(ms), C.byref(n)))
+        return ms.value, n.value
+
+    def reset(self):
+        """Back to the zero terminal value V = 0, u = A (iteration count kept)."""
+        import torch
+        if getattr(self, "_zeros", None) is None:
+            self._zeros = torch.zeros((self.d, self.N ** self.d), dtype=torch.float64, device="cuda")
+        _check(lib().cg_set_state(self.handle, C.c_void_p(self._zeros.data_ptr()), None))
+
+    def destroy(self):
+        if getattr(self, "handle", None):
+            lib().cg_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+# Module-level functions named after the C entry points.
+
+def init_game(game, precision: int = FP64, stream=None) -> ChebGame:
+    return ChebGame(game, precision, stream)
+
+
+def step(g: ChebGame, nsteps: int = 1, sync: bool = True):
+    return g.step(nsteps, sync)
+
+
+def solve(g: ChebGame, max_steps: int, tol: float = 0.0):
+    return g.solve(max_steps, tol)
+
+
+def get_state(g: ChebGame):
+    return g.get_state()
+
+
+def set_state(g: ChebGame, V, U=None):
+    return g.set_state(V, U)
+
+
+def destroy(g: ChebGame):
+    g.destroy()
+
+
+def chebyshev_transform(vals, d: Optional[int] = None, stream=None):
+    """Coefficients of value tensors: vals has shape [batch..., n_0, ..., n_{d-1}]."""
+    import torch
+    d = vals.dim() if d is None else d
+    n = list(vals.shape[vals.dim() - d:])
+    batch = int(np.prod(vals.shape[:vals.dim() - d])) if vals.dim() > d else 1
+    vals = vals.to(dtype=torch.float64).contiguous()
+    out = torch.empty_like(vals)
+    nn = (C.c_int32 * d)(*n)
+    _check(lib().cg_chebyshev_transform(d, nn, C.c_void_p(vals.data_ptr()), C.c_void_p(out.data_ptr()), batch,
+                                        C.c_void_p(_stream(stream))))
+    return out
+
+
+def chebyshev_eval(coef, x, precision: int = FP64, stream=None, out=None):
+    """Series with coefficient tensor coef (shape n_0..n_{d-1}) at the rows of x (npts x d)."""
+    import torch
+    d = coef.dim()
+    n = (C.c_int32 * d)(*coef.shape)
+    coef = coef.to(dtype=torch.float64).contiguous()
+    x = x.to(dtype=torch.float64).contiguous().reshape(-1, d)
+    npts = x.shape[0]
+    odt = torch.float64 if precision == FP64 else torch.float32
+    if out is None:
+        out = torch.empty(npts, dtype=odt, device=coef.device)
+    wsb = int(lib().cg_eval_workspace_bytes(d, n, precision))
+    ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device=coef.device)
+    _check(lib().cg_chebyshev_eval(d, n, C.c_void_p(coef.data_ptr()), C.c_void_p(x.data_ptr()), npts,
+                                   C.c_void_p(out.data_ptr()), precision, C.c_void_p(ws.data_ptr()), wsb,
+                                   C.c_void_p(_stream(stream))))
+    out._ws = ws  # keep the workspace alive with the result's lifetime
+    return out

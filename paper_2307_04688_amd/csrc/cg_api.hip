@@ -1,0 +1,506 @@
+// cg_api.hip -- host side of the C ABI declared in include/chebgame.h.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+#include <vector>
+
+#include "cg_internal.h"
+
+using namespace cg;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *where)
+{
+    return fail(CG_EDEVICE, "%s: %s", where, hipGetErrorString(e));
+}
+
+#define HIP_TRY(call, where)                         \
+    do {                                             \
+        hipError_t e_ = (call);                      \
+        if (e_ != hipSuccess) return hip_fail(e_, where); \
+    } while (0)
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int check_device()
+{
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, dev), "hipGetDeviceProperties");
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(CG_EDEVICE, "device %d is %s; libchebgame is built for gfx950 only", dev, prop.gcnArchName);
+    return CG_OK;
+}
+
+struct Layout {
+    size_t gc, st, V, U, coef, Bp, total;
+};
+
+int validate(const cg_game_desc *g, int precision)
+{
+    if (!g) return fail(CG_EINVAL, "desc is NULL");
+    if (g->d < 2 || g->d > CG_MAX_D) return fail(CG_EUNSUPPORTED, "d = %d outside [2, %d]", g->d, CG_MAX_D);
+    if (g->n_nodes < 3 || g->n_nodes > CG_MAX_N)
+        return fail(CG_EUNSUPPORTED, "n_nodes = %d outside [3, %d]", g->n_nodes, CG_MAX_N);
+    const int nu = g->n_unodes ? g->n_unodes : g->n_nodes;
+    if (nu < 3 || nu > CG_MAX_N) return fail(CG_EUNSUPPORTED, "n_unodes = %d outside [3, %d]", nu, CG_MAX_N);
+    if (g->reserved != 0) return fail(CG_EINVAL, "reserved must be 0");
+    long long NN = 1;
+    for (int l = 0; l < g->d; ++l) NN *= g->n_nodes;
+    if (NN > (1LL << 30)) return fail(CG_EUNSUPPORTED, "N^d too large");
+    if (!(g->h > 0.0) || !isfinite(g->h)) return fail(CG_EINVAL, "h must be finite and > 0");
+    if (!(g->rho * g->h > 0.0 && g->rho * g->h < 1.0)) return fail(CG_EINVAL, "need 0 < rho h < 1");
+    if (!(g->p_max > 0.0) || !isfinite(g->p_max)) return fail(CG_EINVAL, "p_max must be finite and > 0");
+    if (!(g->u_max > 0.0) || !isfinite(g->u_max)) return fail(CG_EINVAL, "u_max must be finite and > 0");
+    if (!g->K || !g->c || !g->beta || !g->A || !g->phi) return fail(CG_EINVAL, "K, c, beta, A, phi are required");
+    for (int i = 0; i < g->d * g->d; ++i)
+        if (!isfinite(g->K[i])) return fail(CG_EINVAL, "K[%d] is not finite", i);
+    for (int i = 0; i < g->d; ++i) {
+        if (!isfinite(g->c[i]) || !isfinite(g->beta[i]) || !isfinite(g->A[i]) || !isfinite(g->phi[i]))
+            return fail(CG_EINVAL, "parameter of player %d is not finite", i);
+        if (g->m && !(g->m[i] > 0.0 && isfinite(g->m[i]))) return fail(CG_EINVAL, "m[%d] must be > 0", i);
+    }
+    if (precision != CG_FP64 && precision != CG_FP32_CORR)
+        return fail(CG_EUNSUPPORTED, "game precision %d not supported (CG_FP64 or CG_FP32_CORR)", precision);
+    return CG_OK;
+}
+
+void dims(const cg_game_desc *g, int &N4, int &NC, int &K, long long &NN)
+{
+    const int N = g->n_nodes;
+    N4 = (N + 3) & ~3;
+    NC = N <= 16 ? 16 : 32;
+    K = N4;
+    for (int l = 0; l < g->d - 2; ++l) K *= N;
+    NN = 1;
+    for (int l = 0; l < g->d; ++l) NN *= N;
+}
+
+Layout layout(const cg_game_desc *g, int precision)
+{
+    int N4, NC, K;
+    long long NN;
+    dims(g, N4, NC, K, NN);
+    (void)precision;
+    Layout L;
+    size_t o = 0;
+    L.gc = o; o = align256(o + sizeof(GameConst));
+    L.st = o; o = align256(o + sizeof(GameStatus));
+    L.V = o; o = align256(o + sizeof(double) * 2 * g->d * NN);
+    L.U = o; o = align256(o + sizeof(double) * 2 * g->d * NN);
+    L.coef = o; o = align256(o + sizeof(double) * g->d * NN);
+    L.Bp = o; o = align256(o + sizeof(double) * (size_t)g->d * K * NC);
+    L.total = o;
+    return L;
+}
+
+double cos_pi_frac(long long a, long long n)
+{
+    long long r = a % (2 * n);
+    if (r < 0) r += 2 * n;
+    return cos(M_PI * (double)r / (double)n);
+}
+
+// DCT-I matrix of size N (eq. (forcoef)) into a kMaxN-strided table.
+void dct1_matrix(int N, double *D)
+{
+    const int n = N - 1;
+    for (int l = 0; l < N; ++l)
+        for (int k = 0; k < N; ++k) {
+            double v = cos_pi_frac((long long)l * k, n);
+            if (k == 0 || k == n) v *= 0.5;
+            D[l * kMaxN + k] = v * ((l == 0 || l == n) ? 1.0 : 2.0) / (double)n;
+        }
+}
+
+}  // namespace
+
+struct cg_game {
+    GameConst hc;       // host copy of the constants
+    Layout L;
+    char *ws;
+    hipStream_t stream;
+    int precision;
+    StepBuffers b;
+    long long launched; // iterations queued (including no-ops after convergence)
+    bool prof;                     // record events around the contraction kernel
+    std::vector<hipEvent_t> evs;   // pairs (begin, end), one pair per profiled launch
+    size_t ev_used;
+    ~cg_game()
+    {
+        for (hipEvent_t e : evs) (void)hipEventDestroy(e);
+    }
+};
+
+namespace {
+
+__global__ void k_fill_state(double *V, double *U, const GameConst *__restrict__ gc, GameStatus *st)
+{
+    const long long n = (long long)gc->d * gc->NN;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < 2 * n;
+         e += (long long)gridDim.x * blockDim.x) {
+        const int i = (int)((e % n) / gc->NN);
+        V[e] = 0.0;
+        U[e] = gc->A[i];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->res_bits[0] = st->res_bits[1] = 0ull;
+        st->last_res = 0.0;
+        st->converged = 0;
+        st->steps_done = 0;
+        st->total_steps = 0;
+        st->cur = 0;
+        st->nonfinite = 0;
+    }
+}
+
+__global__ void k_set_state(double *V, double *U, const double *Vin, const double *Uin,
+                            const GameConst *__restrict__ gc, GameStatus *st)
+{
+    const long long n = (long long)gc->d * gc->NN;
+    const int cur = st->cur;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+         e += (long long)gridDim.x * blockDim.x) {
+        V[cur * n + e] = Vin[e];
+        U[cur * n + e] = Uin ? Uin[e] : gc->A[(int)(e / gc->NN)];
+    }
+}
+
+__global__ void k_get_state(const double *V, const double *U, double *Vout, double *Uout,
+                            const GameConst *__restrict__ gc, const GameStatus *st)
+{
+    const long long n = (long long)gc->d * gc->NN;
+    const int cur = st->cur;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+         e += (long long)gridDim.x * blockDim.x) {
+        if (Vout) Vout[e] = V[cur * n + e];
+        if (Uout) Uout[e] = U[cur * n + e];
+    }
+}
+
+// Reset the convergence test (and set its threshold) before a solve.
+__global__ void k_arm(GameConst *gc, GameStatus *st, double tol, int clear_done)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        gc->tol = tol;
+        st->converged = 0;
+        st->nonfinite = 0;
+        st->res_bits[st->cur] = 0ull;
+        if (clear_done) st->steps_done = 0;
+    }
+}
+
+int read_status(cg_game *g, GameStatus &out)
+{
+    HIP_TRY(hipMemcpyAsync(&out, g->ws + g->L.st, sizeof(GameStatus), hipMemcpyDeviceToHost, g->stream),
+            "hipMemcpyAsync(status)");
+    HIP_TRY(hipStreamSynchronize(g->stream), "hipStreamSynchronize");
+    return CG_OK;
+}
+
+int queue_steps(cg_game *g, int n)
+{
+    for (int s = 0; s < n; ++s) {
+        StepBuffers b = g->b;
+        if (g->prof) {
+            if (g->ev_used + 2 > g->evs.size()) {
+                for (int k = 0; k < 256; ++k) {
+                    hipEvent_t e;
+                    HIP_TRY(hipEventCreate(&e), "hipEventCreate");
+                    g->evs.push_back(e);
+                }
+            }
+            b.ev_begin = g->evs[g->ev_used];
+            b.ev_end = g->evs[g->ev_used + 1];
+            g->ev_used += 2;
+        }
+        hipError_t e = launch_step(g->hc, b, g->stream);
+        if (e != hipSuccess) return hip_fail(e, "step launch");
+    }
+    g->launched += n;
+    return CG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *cg_last_error(void) { return g_last_error.c_str(); }
+
+const char *cg_strerror(int status)
+{
+    switch (status) {
+        case CG_OK: return "ok";
+        case CG_ENOTCONVERGED: return "tolerance not reached within max_steps";
+        case CG_EINVAL: return "invalid argument";
+        case CG_EUNSUPPORTED: return "size or precision not supported";
+        case CG_EDEVICE: return "HIP device error";
+        case CG_ENOMEM: return "workspace too small";
+        case CG_ENONFINITE: return "non-finite value in the iterate";
+    }
+    return "unknown status";
+}
+
+size_t cg_workspace_bytes(const cg_game_desc *desc, int precision)
+{
+    if (validate(desc, precision) != CG_OK) return 0;
+    return layout(desc, precision).total;
+}
+
+int cg_init_game(const cg_game_desc *g, int precision, void *ws_dev, size_t ws_bytes, void *stream,
+                 cg_game **out)
+{
+    if (!out) return fail(CG_EINVAL, "out is NULL");
+    *out = nullptr;
+    int rc = validate(g, precision);
+    if (rc != CG_OK) return rc;
+    rc = check_device();
+    if (rc != CG_OK) return rc;
+    Layout L = layout(g, precision);
+    if (!ws_dev) return fail(CG_EINVAL, "workspace is NULL");
+    if (((uintptr_t)ws_dev & 255) != 0) return fail(CG_EINVAL, "workspace must be 256-byte aligned");
+    if (ws_bytes < L.total) return fail(CG_ENOMEM, "workspace has %zu bytes, needs %zu", ws_bytes, L.total);
+
+    cg_game *G = new (std::nothrow) cg_game();
+    if (!G) return fail(CG_ENOMEM, "host allocation failed");
+    GameConst &hc = G->hc;
+    memset(&hc, 0, sizeof hc);
+    const int d = g->d, N = g->n_nodes, Nu = g->n_unodes ? g->n_unodes : g->n_nodes;
+    hc.d = d;
+    hc.N = N;
+    hc.Nu = Nu;
+    dims(g, hc.N4, hc.NC, hc.K, hc.NN);
+    hc.h = g->h;
+    hc.rho = g->rho;
+    hc.pmax = g->p_max;
+    hc.umax = g->u_max;
+    hc.delta = 1.0 - g->rho * g->h;
+    for (int i = 0; i < d; ++i) {
+        const double mi = g->m ? g->m[i] : 1.0;
+        for (int j = 0; j < d; ++j) hc.M[i * d + j] = g->K[i * d + j] / mi - (i == j ? g->c[i] : 0.0);
+        hc.beta[i] = g->beta[i];
+        hc.A[i] = g->A[i];
+        hc.phi[i] = g->phi[i];
+    }
+    hc.tol = 0.0;
+    for (int k = 0; k < N; ++k) {
+        hc.xnode[k] = cos_pi_frac(k, N - 1);
+        hc.pnode[k] = 0.5 * g->p_max * (hc.xnode[k] + 1.0);
+    }
+    for (int m = 0; m < Nu; ++m) hc.unode[m] = 0.5 * g->u_max * (cos_pi_frac(m, Nu - 1) + 1.0);
+    dct1_matrix(Nu, hc.Du);
+    dct1_matrix(N, hc.Dx);
+
+    G->L = L;
+    G->ws = (char *)ws_dev;
+    G->stream = (hipStream_t)stream;
+    G->precision = precision;
+    G->launched = 0;
+    StepBuffers &b = G->b;
+    b.gc = (const GameConst *)(G->ws + L.gc);
+    b.status = (GameStatus *)(G->ws + L.st);
+    b.V = (double *)(G->ws + L.V);
+    b.U = (double *)(G->ws + L.U);
+    b.coef = (double *)(G->ws + L.coef);
+    b.Bp = (double *)(G->ws + L.Bp);
+    b.Bp32 = nullptr;
+    b.E = nullptr;
+    b.precision = precision;
+    b.ev_begin = b.ev_end = nullptr;
+    G->prof = false;
+    G->ev_used = 0;
+
+    hipError_t e = hipMemcpyAsync(G->ws + L.gc, &hc, sizeof hc, hipMemcpyHostToDevice, G->stream);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_fill_state, dim3(256), dim3(256), 0, G->stream, b.V, b.U, b.gc, b.status);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(G->stream);  // hc must outlive the copy
+    if (e != hipSuccess) {
+        delete G;
+        return hip_fail(e, "cg_init_game");
+    }
+    *out = G;
+    return CG_OK;
+}
+
+int cg_destroy(cg_game *game)
+{
+    delete game;
+    return CG_OK;
+}
+
+int cg_chebyshev_transform(int d, const int32_t *n, const double *vals_dev, double *coef_dev, int64_t batch,
+                           void *stream)
+{
+    if (d < 1 || d > CG_MAX_D) return fail(CG_EUNSUPPORTED, "d = %d outside [1, %d]", d, CG_MAX_D);
+    if (batch < 0) return fail(CG_EINVAL, "batch < 0");
+    if (!n || (batch > 0 && (!vals_dev || !coef_dev))) return fail(CG_EINVAL, "NULL argument");
+    int nn[kMaxD];
+    for (int l = 0; l < d; ++l) {
+        if (n[l] < 2 || n[l] > CG_MAX_N) return fail(CG_EUNSUPPORTED, "n[%d] = %d outside [2, %d]", l, n[l], CG_MAX_N);
+        nn[l] = n[l];
+    }
+    if (batch > 0 && vals_dev == coef_dev) return fail(CG_EINVAL, "vals and coef must not overlap");
+    int rc = check_device();
+    if (rc != CG_OK) return rc;
+    if (batch == 0) return CG_OK;
+    HIP_TRY(run_transform(d, nn, vals_dev, coef_dev, batch, (hipStream_t)stream), "transform launch");
+    return CG_OK;
+}
+
+size_t cg_eval_workspace_bytes(int d, const int32_t *n, int precision)
+{
+    if (d < 1 || d > CG_MAX_D || !n) return 0;
+    int nn[kMaxD];
+    for (int l = 0; l < d; ++l) nn[l] = n[l];
+    return eval_ws_bytes(d, nn, precision);
+}
+
+int cg_chebyshev_eval(int d, const int32_t *n, const double *coef_dev, const double *x_dev, int64_t npts,
+                      void *out_dev, int precision, void *ws_dev, size_t ws_bytes, void *stream)
+{
+    if (d < 1 || d > CG_MAX_D) return fail(CG_EUNSUPPORTED, "d = %d outside [1, %d]", d, CG_MAX_D);
+    if (npts < 0) return fail(CG_EINVAL, "npts < 0");
+    if (!n || !coef_dev || (npts > 0 && (!x_dev || !out_dev))) return fail(CG_EINVAL, "NULL argument");
+    if (precision != CG_FP64 && precision != CG_FP32 && precision != CG_BF16)
+        return fail(CG_EUNSUPPORTED, "eval precision %d not supported", precision);
+    int nn[kMaxD];
+    for (int l = 0; l < d; ++l) {
+        if (n[l] < 2 || n[l] > CG_MAX_N) return fail(CG_EUNSUPPORTED, "n[%d] = %d outside [2, %d]", l, n[l], CG_MAX_N);
+        nn[l] = n[l];
+    }
+    const size_t need = eval_ws_bytes(d, nn, precision);
+    if (need > 0 && (!ws_dev || ws_bytes < need))
+        return fail(CG_ENOMEM, "eval workspace has %zu bytes, needs %zu", ws_dev ? ws_bytes : 0, need);
+    if (need > 0 && ((uintptr_t)ws_dev & 255) != 0) return fail(CG_EINVAL, "workspace must be 256-byte aligned");
+    int rc = check_device();
+    if (rc != CG_OK) return rc;
+    HIP_TRY(launch_eval(d, nn, coef_dev, x_dev, npts, out_dev, precision, ws_dev, ws_bytes, (hipStream_t)stream),
+            "eval launch");
+    return CG_OK;
+}
+
+int cg_step(cg_game *g, int32_t nsteps, double *residual_out)
+{
+    if (!g) return fail(CG_EINVAL, "game is NULL");
+    if (nsteps < 0) return fail(CG_EINVAL, "nsteps < 0");
+    hipLaunchKernelGGL(k_arm, dim3(1), dim3(64), 0, g->stream, (GameConst *)g->b.gc, g->b.status, 0.0, 0);
+    HIP_TRY(hipGetLastError(), "arm launch");
+    int rc = queue_steps(g, nsteps);
+    if (rc != CG_OK) return rc;
+    if (residual_out) {
+        GameStatus st;
+        rc = read_status(g, st);
+        if (rc != CG_OK) return rc;
+        *residual_out = st.last_res;
+        if (st.nonfinite) return fail(CG_ENONFINITE, "non-finite residual after %d steps", st.steps_done);
+    }
+    return CG_OK;
+}
+
+int cg_solve(cg_game *g, int32_t max_steps, double tol, int32_t *steps_done, double *residual)
+{
+    if (!g) return fail(CG_EINVAL, "game is NULL");
+    if (max_steps < 0) return fail(CG_EINVAL, "max_steps < 0");
+    if (!(tol == tol)) return fail(CG_EINVAL, "tol is NaN");
+    hipLaunchKernelGGL(k_arm, dim3(1), dim3(64), 0, g->stream, (GameConst *)g->b.gc, g->b.status,
+                       tol > 0.0 ? tol : 0.0, 1);
+    HIP_TRY(hipGetLastError(), "arm launch");
+    GameStatus st;
+    int rc;
+    if (tol <= 0.0) {
+        rc = queue_steps(g, max_steps);
+        if (rc != CG_OK) return rc;
+        rc = read_status(g, st);
+        if (rc != CG_OK) return rc;
+    } else {
+        // queue in chunks; the device-side test turns the tail of a chunk into no-ops
+        int queued = 0;
+        const int chunk = 32;
+        for (;;) {
+            const int n = max_steps - queued < chunk ? max_steps - queued : chunk;
+            rc = queue_steps(g, n);
+            if (rc != CG_OK) return rc;
+            queued += n;
+            rc = read_status(g, st);
+            if (rc != CG_OK) return rc;
+            if (st.converged || queued >= max_steps) break;
+        }
+    }
+    if (steps_done) *steps_done = st.steps_done;
+    if (residual) *residual = st.last_res;
+    if (st.nonfinite) return fail(CG_ENONFINITE, "non-finite residual after %d steps", st.steps_done);
+    if (tol > 0.0 && !st.converged) return CG_ENOTCONVERGED;
+    return CG_OK;
+}
+
+int cg_get_state(cg_game *g, double *V_dev, double *U_dev, int32_t *r)
+{
+    if (!g) return fail(CG_EINVAL, "game is NULL");
+    if (V_dev || U_dev) {
+        hipLaunchKernelGGL(k_get_state, dim3(256), dim3(256), 0, g->stream, g->b.V, g->b.U, V_dev, U_dev, g->b.gc,
+                           g->b.status);
+        HIP_TRY(hipGetLastError(), "get_state launch");
+    }
+    if (r) {
+        GameStatus st;
+        int rc = read_status(g, st);
+        if (rc != CG_OK) return rc;
+        *r = st.total_steps;
+    }
+    return CG_OK;
+}
+
+int cg_profile(cg_game *g, int enable, double *kernel_ms, int64_t *launches)
+{
+    if (!g) return fail(CG_EINVAL, "game is NULL");
+    if (kernel_ms || launches) {
+        HIP_TRY(hipStreamSynchronize(g->stream), "hipStreamSynchronize");
+        double tot = 0.0;
+        for (size_t k = 0; k + 1 < g->ev_used; k += 2) {
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, g->evs[k], g->evs[k + 1]), "hipEventElapsedTime");
+            tot += ms;
+        }
+        if (kernel_ms) *kernel_ms = tot;
+        if (launches) *launches = (int64_t)(g->ev_used / 2);
+    }
+    g->prof = enable != 0;
+    g->ev_used = 0;
+    return CG_OK;
+}
+
+int cg_set_state(cg_game *g, const double *V_dev, const double *U_dev)
+{
+    if (!g) return fail(CG_EINVAL, "game is NULL");
+    if (!V_dev) return fail(CG_EINVAL, "V is NULL");
+    hipLaunchKernelGGL(k_set_state, dim3(256), dim3(256), 0, g->stream, g->b.V, g->b.U, V_dev, U_dev, g->b.gc,
+                       g->b.status);
+    HIP_TRY(hipGetLastError(), "set_state launch");
+    hipLaunchKernelGGL(k_arm, dim3(1), dim3(64), 0, g->stream, (GameConst *)g->b.gc, g->b.status, 0.0, 0);
+    HIP_TRY(hipGetLastError(), "arm launch");
+    return CG_OK;
+}
+
+}  // extern "C"

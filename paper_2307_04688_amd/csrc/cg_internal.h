@@ -1,0 +1,79 @@
+// cg_internal.h -- shared declarations of libchebgame's gfx950 kernels and
+// the host API that launches them.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/chebgame.h"
+
+namespace cg {
+
+constexpr int kMaxD = CG_MAX_D;
+constexpr int kMaxN = CG_MAX_N;
+constexpr int kWave = 64;
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// Device-resident constants of one game (read through a pointer in the
+// workspace; every field is FP64 or int).
+struct GameConst {
+    int d, N, Nu, N4;          // N4 = N rounded up to a multiple of 4
+    int NC;                    // free-mode columns padded to 16 or 32
+    int K;                     // contraction length per player (padded)
+    long long NN;              // N^d nodes
+    double h, rho, pmax, umax, delta;
+    double M[kMaxD * kMaxD];   // K / m - diag(c), row-major
+    double beta[kMaxD], A[kMaxD], phi[kMaxD];
+    double tol;                // convergence threshold of the device test (<= 0: off)
+    double xnode[kMaxN];       // Lobatto nodes cos(pi k / (N-1))
+    double pnode[kMaxN];       // physical nodes p_max (x + 1) / 2
+    double unode[kMaxN];       // control nodes u_max (cos(pi m / (Nu-1)) + 1) / 2
+    double Du[kMaxN * kMaxN];  // DCT-I matrix of the control fit, [l][m]
+    double Dx[kMaxN * kMaxN];  // DCT-I matrix of the state transform, [l][k]
+};
+
+// Per-game device status words.
+struct GameStatus {
+    unsigned long long res_bits[2];  // residual of the running step, per state buffer, as bits
+    double last_res;                 // residual of the last finished step
+    int converged;                   // set once a residual < tol (or non-finite): later steps are no-ops
+    int steps_done;                  // iterations performed since the last solve started
+    int cur;                         // which of the two state buffers holds V^{[r]}, u^{[r]}
+    int nonfinite;                   // a non-finite residual was produced
+    int total_steps;                 // iterations performed since init
+    int pad;
+};
+
+// ---- launchers (defined in the .hip files) ----
+
+// Mode-m pass of the DCT-I transform over 'batch' tensors of shape n[0..d-1].
+// in and out may alias (the pass loads a whole fiber before writing it).
+hipError_t launch_transform_mode(const double *in, double *out, int d, const int *n, int mode,
+                                 long long batch, const double *D_dev, hipStream_t s);
+
+// Full transform (d passes) using the DCT matrices for each distinct n.
+hipError_t run_transform(int d, const int *n, const double *vals, double *coef, long long batch,
+                         hipStream_t s);
+
+// One value-iteration step of a game (all kernels of Steps 1-4).
+struct StepBuffers {
+    const GameConst *gc;     // device
+    GameStatus *status;      // device
+    double *V, *U;           // two state buffers each, [2][d][NN]; status->cur selects
+    double *coef;            // d * NN, natural layout
+    double *Bp;              // d * K * NC packed operand (FP64)
+    float *Bp32;             // d * K * NC packed remainder operand (FP32 path)
+    double *E;               // FP32_CORR: exact value and first-order tensors
+    int precision;
+    hipEvent_t ev_begin, ev_end;  // recorded around the contraction kernel when non-null
+};
+hipError_t launch_transform_game(const GameConst &hc, const StepBuffers &b, hipStream_t s);
+hipError_t launch_step(const GameConst &hc, const StepBuffers &b, hipStream_t s);
+
+hipError_t launch_eval(int d, const int *n, const double *coef, const double *x, long long npts,
+                       void *out, int precision, void *ws, size_t ws_bytes, hipStream_t s);
+size_t eval_ws_bytes(int d, const int *n, int precision);
+
+}  // namespace cg
