@@ -71,7 +71,8 @@ extern "C" {
 typedef struct cg_game_desc {
     int32_t d;          /* players = state dimension, 2..CG_MAX_D */
     int32_t n_nodes;    /* N: Lobatto nodes per state dimension, 3..CG_MAX_N */
-    int32_t n_unodes;   /* control nodes per player on [0,u_max], 3..CG_MAX_N; 0 = N */
+    int32_t n_unodes;   /* control nodes per player on [0,u_max], 3..N rounded up to a
+                           multiple of 4; 0 = N */
     int32_t reserved;   /* must be 0 */
     double h;           /* time step, > 0 */
     double rho;         /* discount rate; requires 0 < rho h < 1 */

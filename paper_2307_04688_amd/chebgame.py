@@ -119,7 +119,9 @@ class ChebGame:
         desc = _desc(game, keep)
         L = lib()
         nbytes = int(L.cg_workspace_bytes(C.byref(desc), precision))
-        if nbytes == 0:
+        if nbytes == 0:  # invalid description: let init report the specific status
+            h = C.c_void_p()
+            _check(L.cg_init_game(C.byref(desc), precision, None, 0, C.c_void_p(_stream(stream)), C.byref(h)))
             raise ChebGameError(EINVAL, last_error())
         self.ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
         self.stream = stream

@@ -53,7 +53,7 @@ int check_device()
 }
 
 struct Layout {
-    size_t gc, st, V, U, coef, Bp, total;
+    size_t gc, st, V, U, coef, tmp, Bp, W, total;
 };
 
 int validate(const cg_game_desc *g, int precision)
@@ -64,6 +64,8 @@ int validate(const cg_game_desc *g, int precision)
         return fail(CG_EUNSUPPORTED, "n_nodes = %d outside [3, %d]", g->n_nodes, CG_MAX_N);
     const int nu = g->n_unodes ? g->n_unodes : g->n_nodes;
     if (nu < 3 || nu > CG_MAX_N) return fail(CG_EUNSUPPORTED, "n_unodes = %d outside [3, %d]", nu, CG_MAX_N);
+    if (nu > ((g->n_nodes + 3) & ~3))
+        return fail(CG_EUNSUPPORTED, "n_unodes = %d above n_nodes rounded up to a multiple of 4", nu);
     if (g->reserved != 0) return fail(CG_EINVAL, "reserved must be 0");
     long long NN = 1;
     for (int l = 0; l < g->d; ++l) NN *= g->n_nodes;
@@ -109,7 +111,9 @@ Layout layout(const cg_game_desc *g, int precision)
     L.V = o; o = align256(o + sizeof(double) * 2 * g->d * NN);
     L.U = o; o = align256(o + sizeof(double) * 2 * g->d * NN);
     L.coef = o; o = align256(o + sizeof(double) * g->d * NN);
+    L.tmp = o; o = align256(o + sizeof(double) * g->d * NN);
     L.Bp = o; o = align256(o + sizeof(double) * (size_t)g->d * K * NC);
+    L.W = o; o = align256(o + sizeof(double) * (size_t)g->d * NN * NC);
     L.total = o;
     return L;
 }
@@ -153,6 +157,12 @@ struct cg_game {
 };
 
 namespace {
+
+__global__ void k_zero(double *p, long long n)
+{
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x)
+        p[e] = 0.0;
+}
 
 __global__ void k_fill_state(double *V, double *U, const GameConst *__restrict__ gc, GameStatus *st)
 {
@@ -322,7 +332,9 @@ int cg_init_game(const cg_game_desc *g, int precision, void *ws_dev, size_t ws_b
     b.V = (double *)(G->ws + L.V);
     b.U = (double *)(G->ws + L.U);
     b.coef = (double *)(G->ws + L.coef);
+    b.tmp = (double *)(G->ws + L.tmp);
     b.Bp = (double *)(G->ws + L.Bp);
+    b.W = (double *)(G->ws + L.W);
     b.Bp32 = nullptr;
     b.E = nullptr;
     b.precision = precision;
@@ -333,6 +345,10 @@ int cg_init_game(const cg_game_desc *g, int precision, void *ws_dev, size_t ws_b
     hipError_t e = hipMemcpyAsync(G->ws + L.gc, &hc, sizeof hc, hipMemcpyHostToDevice, G->stream);
     if (e == hipSuccess) {
         hipLaunchKernelGGL(k_fill_state, dim3(256), dim3(256), 0, G->stream, b.V, b.U, b.gc, b.status);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_zero, dim3(256), dim3(256), 0, G->stream, b.Bp, (long long)hc.d * hc.K * hc.NC);
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipStreamSynchronize(G->stream);  // hc must outlive the copy

@@ -187,7 +187,7 @@ __global__ __launch_bounds__(256) void k_eval_mfma(const TE *__restrict__ Bp, co
         double w[NC];
 #pragma unroll
         for (int k = 0; k < NC; ++k) w[k] = Wl[row * LDW + k];
-        out[q] = (TO)clenshaw(w, nlast, X[q * D + D - 1]);
+        out[q] = (TO)clenshaw(w, X[q * D + D - 1]);  // columns >= nlast are zero
     }
 }
 
@@ -302,7 +302,7 @@ __global__ __launch_bounds__(256) void k_eval_bf16(const __bf16 *__restrict__ Bp
         double w[NC];
 #pragma unroll
         for (int k = 0; k < NC; ++k) w[k] = Wl[row * LDW + k];
-        out[q] = (float)clenshaw(w, nlast, X[q * D + D - 1]);
+        out[q] = (float)clenshaw(w, X[q * D + D - 1]);  // columns >= nlast are zero
     }
 }
 

@@ -62,8 +62,10 @@ struct StepBuffers {
     const GameConst *gc;     // device
     GameStatus *status;      // device
     double *V, *U;           // two state buffers each, [2][d][NN]; status->cur selects
-    double *coef;            // d * NN, natural layout
+    double *coef;            // d * NN, natural layout (transform intermediate)
+    double *tmp;             // d * NN, transform intermediate
     double *Bp;              // d * K * NC packed operand (FP64)
+    double *W;               // d * NN * NC line coefficients (contraction output)
     float *Bp32;             // d * K * NC packed remainder operand (FP32 path)
     double *E;               // FP32_CORR: exact value and first-order tensors
     int precision;

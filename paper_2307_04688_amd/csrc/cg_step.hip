@@ -14,73 +14,44 @@
 // unfolded with mode i as columns.  The GEMM runs on MFMA (f64 16x16x4);
 // KR_i is generated in registers from per-row recurrences, C_i is read from
 // a packed copy in L2.  The rest of the step (line samples, u-fit, argmax,
-// residual) is per-row work fused after the contraction, so W_i never
-// reaches HBM.
+// residual) is per-row FP64 VALU work with long dependency chains; it runs
+// in a second kernel at its own occupancy, reading W_i back from L2/MALL, so
+// that its registers do not limit the waves of the MFMA kernel.
 #include "cg_line.h"
 
 namespace cg {
 
 // ---------------------------------------------------------------------------
-// Packed contraction operand: Bp[i][kidx][col], kidx enumerating the modes
-// l != i in increasing order with the last of them padded to N4 (zeros), col
-// = k_i padded to NC (zeros).  Written from the natural-layout coefficients.
-__global__ __launch_bounds__(256) void k_pack_B(const GameConst *__restrict__ gc, const GameStatus *st,
-                                                const double *__restrict__ coef, double *__restrict__ Bp)
-{
-    if (st->converged) return;
-    const int d = gc->d, N = gc->N, N4 = gc->N4, NC = gc->NC, K = gc->K;
-    const long long per = (long long)K * NC;
-    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= per * d) return;
-    const int i = (int)(e / per);
-    const int rem = (int)(e % per);
-    const int col = rem % NC;
-    int kidx = rem / NC;
-    const int klast = kidx % N4;
-    kidx /= N4;
-    double v = 0.0;
-    if (klast < N && col < N) {
-        // rebuild the multi-index: others in increasing order, last = klast
-        const int lastmode = (i == d - 1) ? d - 2 : d - 1;
-        int off = 0, mul = 1;
-        for (int l = d - 1; l >= 0; --l) {
-            int k;
-            if (l == i) k = col;
-            else if (l == lastmode) k = klast;
-            else { k = kidx % N; kidx /= N; }
-            off += k * mul;
-            mul *= N;
-        }
-        v = coef[(long long)i * gc->NN + off];
-    }
-    Bp[e] = v;
-}
-
-// ---------------------------------------------------------------------------
-// Fused step kernel, FP64.  Block = 4 waves; wave w owns RB row blocks of 16
-// nodes of one player.  Lane layout of v_mfma_f64_16x16x4f64: A[r][k] and
-// B[k][c] come from lane r + 16 k (resp. c + 16 k); D[g + 4 v][c] sits in
-// lane c + 16 g, element v (rows interleaved by 4, unlike the f32 forms).
+// Contraction kernel, FP64: W_i = KR_i * C_i for one tile of rows.  Block = 4
+// waves; wave w owns RB row blocks of 16 nodes of one player.  Lane layout
+// of v_mfma_f64_16x16x4f64: A[r][k] and B[k][c] come from lane r + 16 k
+// (resp. c + 16 k); D[g + 4 v][c] sits in lane c + 16 g, element v (rows
+// interleaved by 4, unlike the f32 forms).
+//
+// The packed operand of the player (K x NC) streams through LDS in slabs of
+// N4 rows (one value of the outer modes), double-buffered: the block loads
+// slab s+1 into registers while its waves run the MFMAs of slab s.  The
+// result rows go to W[i][j][0..NC) (L2/MALL-resident) for the line kernel.
 template <int D, int N4, int NC, int RB>
-__global__ __launch_bounds__(256) void k_step_f64(const GameConst *__restrict__ gc, GameStatus *st,
-                                                  double *Vbuf, double *Ubuf, const double *__restrict__ Bp,
-                                                  int blocks_per_player)
+__global__ __launch_bounds__(256) void k_contract_f64(const GameConst *__restrict__ gc, const GameStatus *st,
+                                                      const double *__restrict__ Ubuf,
+                                                      const double *__restrict__ Bp, double *__restrict__ Wout,
+                                                      int blocks_per_player)
 {
     constexpr int NCB = NC / 16;
     constexpr int ROWS_W = RB * 16;
     constexpr int ROWS_B = 4 * ROWS_W;
-    constexpr int LDW = NC + 1;
-    __shared__ double Wl[ROWS_B * LDW];
-    __shared__ double red[4];
+    constexpr int LDB = NC == 32 ? 48 : 16;       // slab rows: kq groups on disjoint banks
+    constexpr int SLAB = N4 * LDB;
+    constexpr int SLAB_E2 = N4 * NC / 2;          // double2 elements per slab
+    constexpr int PF = (SLAB_E2 + 255) / 256;     // double2 prefetch registers per thread
+    __shared__ double lds[2 * SLAB];
 
     if (st->converged) return;
     const int cur = st->cur;
     const int NN = (int)gc->NN;
     const int N = gc->N;
-    const double *Vold = Vbuf + (long long)cur * D * NN;
     const double *Uold = Ubuf + (long long)cur * D * NN;
-    double *Vnew = Vbuf + (long long)(1 - cur) * D * NN;
-    double *Unew = Ubuf + (long long)(1 - cur) * D * NN;
 
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int r16 = lane & 15, kq = lane >> 4;
@@ -88,12 +59,11 @@ __global__ __launch_bounds__(256) void k_step_f64(const GameConst *__restrict__ 
     const int tile = blockIdx.x % blocks_per_player;
     const int row0 = tile * ROWS_B + wave * ROWS_W;
 
-    // other modes in increasing order
-    int om[D - 1];
+    int om[D - 1];  // other modes in increasing order
 #pragma unroll
     for (int t = 0; t < D - 1; ++t) om[t] = t < player ? t : t + 1;
 
-    // ---- prologue: shifted coordinates and basis values of each row ----
+    // ---- shifted coordinates and basis values of each row ----
     double xo[RB][D - 1];
     double Tl[RB][N4 / 4];
 #pragma unroll
@@ -110,7 +80,7 @@ __global__ __launch_bounds__(256) void k_step_f64(const GameConst *__restrict__ 
             xo[rb][t] = 2.0 * y / gc->pmax - 1.0;
         }
         const double xl = xo[rb][D - 2];
-        double tm1 = 1.0, t0 = xl;  // T_0, T_1
+        double tm1 = 1.0, t0 = xl;
 #pragma unroll
         for (int k = 0; k < N4; ++k) {
             double tk;
@@ -121,29 +91,52 @@ __global__ __launch_bounds__(256) void k_step_f64(const GameConst *__restrict__ 
         }
     }
 
-    // ---- contraction on MFMA ----
     f64x4 acc[RB][NCB];
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
         for (int c = 0; c < NCB; ++c) acc[rb][c] = f64x4{0.0, 0.0, 0.0, 0.0};
 
-    const double *B = Bp + (long long)player * gc->K * NC;
-    // outer modes: D == 3 -> om[0]; D == 4 -> om[0] (slow), om[1] (fast)
+    const double2 *Bg = reinterpret_cast<const double2 *>(Bp + (long long)player * gc->K * NC);
+    double2 pf[PF];
+    auto load_slab = [&](int oc) {
+#pragma unroll
+        for (int q = 0; q < PF; ++q) {
+            const int e2 = tid + q * 256;
+            if (e2 < SLAB_E2) pf[q] = Bg[(long long)oc * SLAB_E2 + e2];
+        }
+    };
+    auto store_slab = [&](double *buf) {
+#pragma unroll
+        for (int q = 0; q < PF; ++q) {
+            const int e2 = tid + q * 256;
+            if (e2 < SLAB_E2) {
+                const int e = 2 * e2, r = e / NC, c = e % NC;
+                buf[r * LDB + c] = pf[q].x;
+                buf[r * LDB + c + 1] = pf[q].y;
+            }
+        }
+    };
+
     double Ta_prev[RB], Ta[RB], Tb_prev[RB], Tb[RB];
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb) { Ta_prev[rb] = 0.0; Ta[rb] = 1.0; Tb_prev[rb] = 0.0; Tb[rb] = 1.0; }
     const int n_outer = (D == 2) ? 1 : (D == 3 ? N : N * N);
+    load_slab(0);
+    store_slab(lds);
+    __syncthreads();
     for (int oc = 0; oc < n_outer; ++oc) {
+        const double *cb = lds + (oc & 1) * SLAB;
+        const bool more = oc + 1 < n_outer;
+        if (more) load_slab(oc + 1);
         double F[RB];
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) F[rb] = (D == 2) ? 1.0 : (D == 3 ? Ta[rb] : Ta[rb] * Tb[rb]);
-        const double *Brow = B + (long long)oc * N4 * NC + kq * NC + r16;
 #pragma unroll
         for (int t = 0; t < N4 / 4; ++t) {
             double bf[NCB];
 #pragma unroll
-            for (int c = 0; c < NCB; ++c) bf[c] = Brow[t * 4 * NC + c * 16];
+            for (int c = 0; c < NCB; ++c) bf[c] = cb[(4 * t + kq) * LDB + c * 16 + r16];
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb) {
                 const double a = F[rb] * Tl[rb][t];
@@ -177,37 +170,93 @@ __global__ __launch_bounds__(256) void k_step_f64(const GameConst *__restrict__ 
                 }
             }
         }
+        if (more) store_slab(lds + ((oc + 1) & 1) * SLAB);
+        __syncthreads();
     }
 
-    // ---- accumulators to LDS: row-major [row][col] per block ----
+    // ---- rows to W: element v of lane c + 16 kq is row kq + 4 v ----
+    double *Wp = Wout + (long long)player * NN * NC;
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-        for (int c = 0; c < NCB; ++c)
+        for (int v = 0; v < 4; ++v) {
+            const int j = row0 + rb * 16 + kq + 4 * v;
+            if (j < NN) {
 #pragma unroll
-            for (int v = 0; v < 4; ++v)
-                Wl[(wave * ROWS_W + rb * 16 + kq + 4 * v) * LDW + c * 16 + r16] = acc[rb][c][v];
-    __syncthreads();
+                for (int c = 0; c < NCB; ++c) Wp[(long long)j * NC + c * 16 + r16] = acc[rb][c][v];
+            }
+        }
+}
 
-    // ---- epilogue: one thread per (player, node) ----
-    double resmax = 0.0;
-    for (int row = tid; row < ROWS_B; row += 256) {
-        const int j = tile * ROWS_B + row;
-        if (j >= NN) continue;
-        double w[N4];
+// ---------------------------------------------------------------------------
+// Line kernel: Steps 2-4 at every (player, node) from the line coefficients
+// W[i][j][0..NC): fit in u, argmax, new value and control, residual.
+// COMPOSE (control nodes >= N): one thread per row computes the fit
+// coefficients directly (line_compose).  Otherwise two threads share a row:
+// each samples half of the control nodes, and the partial fits are summed
+// through LDS.
+template <int D, int N4, int NC, bool COMPOSE>
+__global__ __launch_bounds__(256) void k_line_f64(const GameConst *__restrict__ gc, GameStatus *st, double *Vbuf,
+                                                  double *Ubuf, const double *__restrict__ Win,
+                                                  int blocks_per_player)
+{
+    constexpr int TPR = COMPOSE ? 1 : 2;
+    constexpr int ROWS_B = 256 / TPR;
+    __shared__ double Qx[COMPOSE ? 1 : N4 * ROWS_B];
+    __shared__ double red[4];
+
+    if (st->converged) return;
+    const int cur = st->cur;
+    const int NN = (int)gc->NN;
+    const double *Vold = Vbuf + (long long)cur * D * NN;
+    const double *Uold = Ubuf + (long long)cur * D * NN;
+    double *Vnew = Vbuf + (long long)(1 - cur) * D * NN;
+    double *Unew = Ubuf + (long long)(1 - cur) * D * NN;
+
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int player = blockIdx.x / blocks_per_player;
+    const int tile = blockIdx.x % blocks_per_player;
+    const int row = tid % ROWS_B;
+    const int part = tid / ROWS_B;
+    const int j = tile * ROWS_B + row;
+    const int jc = j < NN ? j : NN - 1;
+
+    double w[N4];
+    const double2 *wr = reinterpret_cast<const double2 *>(Win + ((long long)player * NN + jc) * NC);
 #pragma unroll
-        for (int k = 0; k < N4; ++k) w[k] = Wl[row * LDW + k];
-        double p[D], ub[D], b[D];
-        node_state<D>(gc, Uold, j, p, ub, b);
-        double vn, un;
-        line_update<D, N4>(gc, player, p, ub, b, w, vn, un);
+    for (int k = 0; k < N4 / 2; ++k) {
+        const double2 t = wr[k];
+        w[2 * k] = t.x;
+        w[2 * k + 1] = t.y;
+    }
+    double p[D], ub[D], b[D];
+    node_state<D>(gc, Uold, jc, p, ub, b);
+    double q[N4];
+    if constexpr (COMPOSE) {
+        line_compose<D, N4>(gc, player, p, ub, b, w, q);
+    } else {
+        line_fit_regs<D, N4, N4>(gc, player, p, ub, b, w, part, 2, q);
+        if (part == 1) {
+#pragma unroll
+            for (int l = 0; l < N4; ++l) Qx[l * ROWS_B + row] = q[l];
+        }
+        __syncthreads();
+        if (part == 0) {
+#pragma unroll
+            for (int l = 0; l < N4; ++l) q[l] += Qx[l * ROWS_B + row];
+        }
+    }
+    double resmax = 0.0;
+    if (part == 0 && j < NN) {
+        const double s0 = 2.0 * ub[player] / gc->umax - 1.0;
+        double s;
+        const double vn = line_argmax(q, gc->Nu, s0, s);
+        const double un = 0.5 * gc->umax * (s + 1.0);
         const long long o = (long long)player * NN + j;
         Vnew[o] = vn;
         Unew[o] = un;
-        const double e = fabs(vn - Vold[o]);
-        resmax = (e > resmax || e != e) ? e : resmax;
+        resmax = fabs(vn - Vold[o]);  // a NaN stays NaN and wins the bitwise max below
     }
-    // block max of the residual; NaN propagates as the largest bit pattern
     unsigned long long bits = __double_as_longlong(resmax);
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
@@ -218,8 +267,8 @@ __global__ __launch_bounds__(256) void k_step_f64(const GameConst *__restrict__ 
     __syncthreads();
     if (tid == 0) {
         unsigned long long m = 0;
-        for (int w = 0; w < 4; ++w) {
-            const unsigned long long x = __double_as_longlong(red[w]);
+        for (int w2 = 0; w2 < 4; ++w2) {
+            const unsigned long long x = __double_as_longlong(red[w2]);
             m = x > m ? x : m;
         }
         atomicMax(&st->res_bits[cur], m);
@@ -252,13 +301,30 @@ template <int D, int N4>
 static hipError_t launch_step_dn(const GameConst &hc, const StepBuffers &b, hipStream_t s)
 {
     constexpr int NC = N4 <= 16 ? 16 : 32;
-    // 32 rows per wave for large grids (fills the chip evenly), 16 otherwise
+    constexpr int RB = 2;  // 32 rows per wave
     const int NN = (int)hc.NN;
-    constexpr int RB = 2;
-    const int rows_b = 4 * RB * 16;
-    const int bpp = (NN + rows_b - 1) / rows_b;
-    hipLaunchKernelGGL((k_step_f64<D, N4, NC, RB>), dim3(bpp * D), dim3(256), 0, s, b.gc, b.status, b.V,
-                       b.U, b.Bp, bpp);
+    const int bpp = (NN + 4 * RB * 16 - 1) / (4 * RB * 16);
+    if (b.ev_begin) {
+        hipError_t e = hipEventRecord(b.ev_begin, s);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((k_contract_f64<D, N4, NC, RB>), dim3(bpp * D), dim3(256), 0, s, b.gc, b.status, b.U, b.Bp,
+                       b.W, bpp);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (b.ev_end) {
+        e = hipEventRecord(b.ev_end, s);
+        if (e != hipSuccess) return e;
+    }
+    if (hc.Nu >= hc.N) {  // the fit in u is exact: compose the series directly
+        const int lpp = (NN + 255) / 256;
+        hipLaunchKernelGGL((k_line_f64<D, N4, NC, true>), dim3(lpp * D), dim3(256), 0, s, b.gc, b.status, b.V, b.U,
+                           b.W, lpp);
+    } else {
+        const int lpp = (NN + 127) / 128;
+        hipLaunchKernelGGL((k_line_f64<D, N4, NC, false>), dim3(lpp * D), dim3(256), 0, s, b.gc, b.status, b.V, b.U,
+                           b.W, lpp);
+    }
     return hipGetLastError();
 }
 
@@ -280,23 +346,10 @@ static hipError_t launch_step_d(const GameConst &hc, const StepBuffers &b, hipSt
 
 hipError_t launch_step(const GameConst &hc, const StepBuffers &b, hipStream_t s)
 {
-    // 1. coefficients of every V_i (Algorithm Cnv), natural layout
+    // 1. coefficients of every V_i (Algorithm Cnv) into the packed operand
     hipError_t e = launch_transform_game(hc, b, s);
     if (e != hipSuccess) return e;
-    // 2. packed operand
-    {
-        const long long total = (long long)hc.d * hc.K * hc.NC;
-        const int threads = 256;
-        hipLaunchKernelGGL(k_pack_B, dim3((unsigned)((total + threads - 1) / threads)), dim3(threads), 0, s,
-                           b.gc, b.status, b.coef, b.Bp);
-        e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
-    // 3. fused contraction + line update + residual
-    if (b.ev_begin) {
-        e = hipEventRecord(b.ev_begin, s);
-        if (e != hipSuccess) return e;
-    }
+    // 2. contraction (MFMA), then line fit + argmax + residual
     switch (hc.d) {
         case 2: e = launch_step_d<2>(hc, b, s); break;
         case 3: e = launch_step_d<3>(hc, b, s); break;
@@ -304,11 +357,7 @@ hipError_t launch_step(const GameConst &hc, const StepBuffers &b, hipStream_t s)
         default: return hipErrorInvalidValue;
     }
     if (e != hipSuccess) return e;
-    if (b.ev_end) {
-        e = hipEventRecord(b.ev_end, s);
-        if (e != hipSuccess) return e;
-    }
-    // 4. bookkeeping
+    // 3. bookkeeping
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, s, b.gc, b.status);
     return hipGetLastError();
 }
