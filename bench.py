@@ -38,6 +38,26 @@ def cpu_baseline(g, steps: int):
                       f"value ({dt:.1f} s), scaled to {TIME_STEPS} steps"}
 
 
+def measured_traffic(key: str):
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE runs (profiles/traffic.json, each counter scaled
+    by its reading for a plain 1 GiB copy), or None once the kernel sources
+    differ from the ones measured."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path)).get(key)
+    if rec is None:
+        return None
+    h = hashlib.sha256()
+    for src in rec["sources"]:
+        h.update(open(os.path.join(ROOT, src), "rb").read())
+    if h.hexdigest()[:16] != rec["source_sha256_16"]:
+        return None
+    return rec["hbm_bytes_per_launch"]
+
+
 def err_vs_reference(G, g):
     """Max |V - V_oracle| / max|V_oracle| on the sampled nodes of the committed
     200-step oracle reference (tests/golden/c2_oracle_reference.json)."""
@@ -64,7 +84,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32corr"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=2, help="oracle iterations timed for the CPU baseline")
+    ap.add_argument("--cpu-steps", type=int, default=6, help="oracle iterations timed for the CPU baseline")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for scaling rocprof byte counters)")
     args = ap.parse_args()
@@ -106,8 +126,9 @@ def main():
     avg_ms = kernel_ms / max(launches, 1)
     achieved = flops_launch / (avg_ms * 1e-3) / 1e12
     peak = PEAK["fp64"] if prec == cg.FP64 else PEAK["fp32"]
+    kname = "k_contract_f64" if prec == cg.FP64 else "k_contract_corr"
     roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-            "traffic": None, "kernel": "k_step_f64" if prec == cg.FP64 else "k_step_mixed",
+            "traffic": measured_traffic(f"{kname} d={g.d} N={g.N}"), "kernel": kname,
             "avg_launch_ms": avg_ms, "launches": launches, "flops_per_launch": flops_launch}
 
     err = err_vs_reference(G, g)
