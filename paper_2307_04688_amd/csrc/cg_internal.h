@@ -43,7 +43,7 @@ struct GameStatus {
     int cur;                         // which of the two state buffers holds V^{[r]}, u^{[r]}
     int nonfinite;                   // a non-finite residual was produced
     int total_steps;                 // iterations performed since init
-    int pad;
+    unsigned int blocks_done;        // blocks of the running line kernel that have finished
 };
 
 // ---- launchers (defined in the .hip files) ----

@@ -188,6 +188,26 @@ __global__ __launch_bounds__(256) void k_contract_f64(const GameConst *__restric
         }
 }
 
+// End of a step, run by the last block of the line kernel once every block
+// has merged its residual: record the residual, test convergence and
+// finiteness, flip the state buffers, clear the next residual slot.
+__device__ void finish_step(const GameConst *__restrict__ gc, GameStatus *st, int cur)
+{
+    const double r = __longlong_as_double(atomicMax(&st->res_bits[cur], 0ull));
+    st->steps_done += 1;
+    st->total_steps += 1;
+    st->last_res = r;
+    if (!(r <= 1.7976931348623157e308)) {
+        st->nonfinite = 1;
+        st->converged = 1;
+    } else if (gc->tol > 0.0 && r < gc->tol) {
+        st->converged = 1;
+    }
+    st->res_bits[1 - cur] = 0ull;
+    st->cur = 1 - cur;
+    atomicExch(&st->blocks_done, 0u);
+}
+
 // ---------------------------------------------------------------------------
 // Line kernel: Steps 2-4 at every (player, node) from the line coefficients
 // W[i][j][0..NC): fit in u, argmax, new value and control, residual.
@@ -272,31 +292,14 @@ __global__ __launch_bounds__(256) void k_line_f64(const GameConst *__restrict__ 
             m = x > m ? x : m;
         }
         atomicMax(&st->res_bits[cur], m);
+        __threadfence();
+        if (atomicAdd(&st->blocks_done, 1u) == gridDim.x - 1) {
+            __threadfence();
+            finish_step(gc, st, cur);
+        }
     }
 }
 
-// End of a step: record the residual, test convergence and finiteness, flip
-// the state buffers, clear the next residual slot.
-__global__ void k_finish(const GameConst *__restrict__ gc, GameStatus *st)
-{
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    if (st->converged) return;
-    const int cur = st->cur;
-    const double r = __longlong_as_double(st->res_bits[cur]);
-    st->steps_done += 1;
-    st->total_steps += 1;
-    st->last_res = r;
-    if (!(r <= 1.7976931348623157e308)) {
-        st->nonfinite = 1;
-        st->converged = 1;
-    } else if (gc->tol > 0.0 && r < gc->tol) {
-        st->converged = 1;
-    }
-    st->cur = 1 - cur;
-    st->res_bits[1 - cur] = 0ull;
-}
-
-// ---------------------------------------------------------------------------
 template <int D, int N4>
 static hipError_t launch_step_dn(const GameConst &hc, const StepBuffers &b, hipStream_t s)
 {
@@ -349,17 +352,14 @@ hipError_t launch_step(const GameConst &hc, const StepBuffers &b, hipStream_t s)
     // 1. coefficients of every V_i (Algorithm Cnv) into the packed operand
     hipError_t e = launch_transform_game(hc, b, s);
     if (e != hipSuccess) return e;
-    // 2. contraction (MFMA), then line fit + argmax + residual
+    // 2. contraction (MFMA), then line fit + argmax + residual + bookkeeping
     switch (hc.d) {
         case 2: e = launch_step_d<2>(hc, b, s); break;
         case 3: e = launch_step_d<3>(hc, b, s); break;
         case 4: e = launch_step_d<4>(hc, b, s); break;
         default: return hipErrorInvalidValue;
     }
-    if (e != hipSuccess) return e;
-    // 3. bookkeeping
-    hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, s, b.gc, b.status);
-    return hipGetLastError();
+    return e;
 }
 
 }  // namespace cg

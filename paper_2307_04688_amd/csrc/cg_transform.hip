@@ -72,69 +72,164 @@ hipError_t run_transform(int d, const int *n, const double *vals, double *coef, 
     return hipSuccess;
 }
 
-// Game transform, one mode per launch, one thread per output coefficient:
-//   out[i][.., l, ..] = sum_k Dx[l][k] in[i][.., k, ..]
-// Mode 0 reads the current state buffer (chosen on the device by the status
-// word); the last pass writes the packed contraction operand of each player
-// directly: Bp[i][kidx][col] with col = k_i and kidx enumerating the other
-// modes in increasing order, the last of them padded to N4 (the padding
-// entries are zero from initialisation and never written).
-__global__ __launch_bounds__(256) void k_transform_pass(const GameConst *__restrict__ gc, const GameStatus *st,
-                                                        const double *Vbuf, const double *in, double *out,
-                                                        double *Bp, int mode, int last)
+// Game transform in two launches, both tiled through LDS.
+//  1. k_tf_fast: the two fastest modes (d-2, d-1) of every N x N slice:
+//     S -> D S D^T.  For d = 2 that is the whole transform and the result goes
+//     straight to the packed operand.
+//  2. k_tf_outer (d >= 3): the remaining modes 0..d-3 on a tile of N^(d-2)
+//     fibres x Q consecutive inner positions, then the packed operand:
+//     Bp[i][kidx][col], col = k_i, kidx enumerating the other modes in
+//     increasing order with the last of them padded to N4 (padding entries are
+//     zero from initialisation and never written).
+__device__ __forceinline__ long long packed_index(const GameConst *__restrict__ gc, int i, const int *dig)
 {
-    __shared__ double Dm[kMaxN * kMaxN];
-    if (st->converged) return;
-    const int N = gc->N, d = gc->d;
-    for (int e = threadIdx.x; e < N * N; e += blockDim.x) Dm[e] = gc->Dx[(e / N) * kMaxN + e % N];
-    __syncthreads();
-    const int NN = (int)gc->NN;
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= d * NN) return;
-    const int i = t / NN, idx = t % NN;
-    int stride = 1;
-    for (int l = mode + 1; l < d; ++l) stride *= N;
-    const int lo = (idx / stride) % N;
-    const int base = idx - lo * stride;
-    const double *src = (mode == 0 ? Vbuf + (long long)st->cur * d * NN : in) + (long long)i * NN + base;
-    const double *Drow = Dm + lo * N;
-    double acc = 0.0;
-    for (int k = 0; k < N; ++k) acc = fma(Drow[k], src[(long long)k * stride], acc);
-    if (!last) {
-        out[t] = acc;
-        return;
-    }
+    const int d = gc->d, N = gc->N;
     const int lastother = (i == d - 1) ? d - 2 : d - 1;
-    int rem = idx, col = 0, kl = 0, kout = 0, mul = 1;
-    int dig[kMaxD];
-    for (int l = d - 1; l >= 0; --l) { dig[l] = rem % N; rem /= N; }
+    int col = 0, kl = 0, kout = 0;
     for (int l = 0; l < d; ++l) {
         if (l == i) col = dig[l];
         else if (l == lastother) kl = dig[l];
         else kout = kout * N + dig[l];
     }
-    (void)mul;
-    const long long kidx = (long long)kout * gc->N4 + kl;
-    Bp[((long long)i * gc->K + kidx) * gc->NC + col] = acc;
+    return ((long long)i * gc->K + (long long)kout * gc->N4 + kl) * gc->NC + col;
+}
+
+__global__ __launch_bounds__(256) void k_tf_fast(const GameConst *__restrict__ gc, const GameStatus *st,
+                                                 const double *Vbuf, double *out, double *Bp)
+{
+    constexpr int LD = kMaxN + 1;  // odd stride: column reads hit distinct banks
+    __shared__ double Dm[kMaxN * LD];
+    __shared__ double X[kMaxN * LD];
+    __shared__ double Y[kMaxN * LD];
+    if (st->converged) return;
+    const int N = gc->N, d = gc->d, NN2 = N * N;
+    const long long NN = gc->NN;
+    const int nslice = (int)(NN / NN2);
+    const int i = blockIdx.x / nslice, sl = blockIdx.x % nslice;
+    const double *src = Vbuf + (long long)st->cur * d * NN + (long long)i * NN + (long long)sl * NN2;
+    for (int e = threadIdx.x; e < NN2; e += blockDim.x) {
+        Dm[(e / N) * LD + e % N] = gc->Dx[(e / N) * kMaxN + e % N];
+        X[(e / N) * LD + e % N] = src[e];
+    }
+    __syncthreads();
+    // Y = D X (mode d-2), then Z = Y D^T (mode d-1).  Each thread owns the
+    // outputs e = tid + 256 u, u < 4 (N^2 <= 1024), run as four independent
+    // accumulation chains.
+    const int tid = threadIdx.x;
+    {
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        int lrow[4], ccol[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = tid + 256 * u;
+            lrow[u] = e < NN2 ? e / N : 0;
+            ccol[u] = e < NN2 ? e % N : 0;
+        }
+        for (int k = 0; k < N; ++k) {
+            const double *Xk = X + k * LD;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acc[u] = fma(Dm[lrow[u] * LD + k], Xk[ccol[u]], acc[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (tid + 256 * u < NN2) Y[lrow[u] * LD + ccol[u]] = acc[u];
+    }
+    __syncthreads();
+    {
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        int rrow[4], lcol[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = tid + 256 * u;
+            rrow[u] = e < NN2 ? e / N : 0;
+            lcol[u] = e < NN2 ? e % N : 0;
+        }
+        for (int k = 0; k < N; ++k) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acc[u] = fma(Y[rrow[u] * LD + k], Dm[lcol[u] * LD + k], acc[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = tid + 256 * u;
+            if (e >= NN2) continue;
+            if (d > 2) {
+                out[(long long)i * NN + (long long)sl * NN2 + e] = acc[u];
+            } else {
+                int dig[kMaxD] = {rrow[u], lcol[u], 0, 0};
+                Bp[packed_index(gc, i, dig)] = acc[u];
+            }
+        }
+    }
+}
+
+// Tile of the outer modes: X[f][q], f over the N^(d-2) outer positions,
+// q over Q consecutive inner positions (the two fast modes flattened).
+__global__ __launch_bounds__(256) void k_tf_outer(const GameConst *__restrict__ gc, const GameStatus *st,
+                                                  const double *__restrict__ in, double *Bp, int Q)
+{
+    extern __shared__ double sh[];
+    if (st->converged) return;
+    const int N = gc->N, d = gc->d, NN2 = N * N;
+    const long long NN = gc->NN;
+    const int F = (int)(NN / NN2);          // N^(d-2) outer positions
+    const int nq = (NN2 + Q - 1) / Q;       // tiles per player
+    const int i = blockIdx.x / nq, q0 = (blockIdx.x % nq) * Q;
+    constexpr int LD = kMaxN + 1;
+    double *Dm = sh;                        // N x N, row stride LD
+    double *X = sh + kMaxN * LD;            // F x Q
+    double *Y = X + F * Q;                  // F x Q (d == 4 intermediate)
+    const double *src = in + (long long)i * NN;
+    for (int e = threadIdx.x; e < NN2; e += blockDim.x) Dm[(e / N) * LD + e % N] = gc->Dx[(e / N) * kMaxN + e % N];
+    for (int e = threadIdx.x; e < F * Q; e += blockDim.x) {
+        const int f = e / Q, q = q0 + e % Q;
+        X[e] = q < NN2 ? src[(long long)f * NN2 + q] : 0.0;
+    }
+    __syncthreads();
+    if (d == 3) {  // mode 0
+        for (int e = threadIdx.x; e < F * Q; e += blockDim.x) {
+            const int l = e / Q, qq = e % Q, q = q0 + qq;
+            if (q >= NN2) continue;
+            double acc = 0.0;
+            for (int k = 0; k < N; ++k) acc = fma(Dm[l * LD + k], X[k * Q + qq], acc);
+            int dig[kMaxD] = {l, q / N, q % N, 0};
+            Bp[packed_index(gc, i, dig)] = acc;
+        }
+    } else {  // d == 4: mode 0 then mode 1; f = a * N + b
+        for (int e = threadIdx.x; e < F * Q; e += blockDim.x) {
+            const int la = e / (N * Q), b = (e / Q) % N, qq = e % Q;
+            double acc = 0.0;
+            for (int k = 0; k < N; ++k) acc = fma(Dm[la * LD + k], X[(k * N + b) * Q + qq], acc);
+            Y[e] = acc;
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < F * Q; e += blockDim.x) {
+            const int a = e / (N * Q), lb = (e / Q) % N, qq = e % Q, q = q0 + qq;
+            if (q >= NN2) continue;
+            double acc = 0.0;
+            for (int k = 0; k < N; ++k) acc = fma(Dm[lb * LD + k], Y[(a * N + k) * Q + qq], acc);
+            int dig[kMaxD] = {a, lb, q / N, q % N};
+            Bp[packed_index(gc, i, dig)] = acc;
+        }
+    }
 }
 
 hipError_t launch_transform_game(const GameConst &hc, const StepBuffers &b, hipStream_t s)
 {
-    const long long total = hc.NN * hc.d;
-    const int threads = 256;
-    const unsigned blocks = (unsigned)((total + threads - 1) / threads);
-    // ping-pong: V -> tmp -> coef -> tmp ... ; the last pass writes Bp
-    const double *in = nullptr;
-    for (int m = 0; m < hc.d; ++m) {
-        const int last = (m == hc.d - 1);
-        double *out = (m % 2 == 0) ? b.tmp : b.coef;
-        hipLaunchKernelGGL(k_transform_pass, dim3(blocks), dim3(threads), 0, s, b.gc, b.status, b.V, in, out, b.Bp,
-                           m, last);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-        in = out;
-    }
-    return hipSuccess;
+    const int N = hc.N, d = hc.d;
+    const long long nslice = hc.NN / (N * N);
+    hipLaunchKernelGGL(k_tf_fast, dim3((unsigned)(nslice * d)), dim3(256), 0, s, b.gc, b.status, b.V, b.tmp, b.Bp);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || d == 2) return e;
+    // Q inner positions per tile, so that the dynamic LDS (D plus one or two
+    // F x Q tiles) stays within 64 KiB
+    const int F = (int)nslice;
+    const int tiles = d == 4 ? 2 : 1;
+    int Q = (8192 - kMaxN * (kMaxN + 1)) / (tiles * F);
+    Q = Q > 16 ? 16 : (Q < 1 ? 1 : Q);
+    const size_t shmem = sizeof(double) * ((size_t)kMaxN * (kMaxN + 1) + (size_t)tiles * F * Q);
+    const int nq = (N * N + Q - 1) / Q;
+    hipLaunchKernelGGL(k_tf_outer, dim3((unsigned)(nq * d)), dim3(256), shmem, s, b.gc, b.status, b.tmp, b.Bp, Q);
+    return hipGetLastError();
 }
 
 }  // namespace cg

@@ -139,7 +139,8 @@ def test_first_step_closed_form(cg, d, N):
 
 @pytest.mark.parametrize("d,N,scale,p_max", [(2, 7, 0.3, 1.0), (2, 16, 0.05, 1.0), (3, 6, 0.2, 1.0),
                                              (3, 9, 0.1, 0.8), (4, 5, 0.2, 1.0), (2, 5, 1.0, 2.0),
-                                             (3, 32, 0.02, 1.0), (4, 8, 0.05, 1.0)])
+                                             (3, 32, 0.02, 1.0), (4, 8, 0.05, 1.0), (4, 24, 0.02, 1.0),
+                                             (4, 13, 0.05, 1.0)])
 def test_one_step_from_random_state(cg, orc, d, N, scale, p_max):
     say("one step random", d, N, scale)
     g = W.make_game(d, N, seed=50 + d + N, per_player=True, p_max=p_max)
@@ -152,7 +153,7 @@ def test_one_step_from_random_state(cg, orc, d, N, scale, p_max):
     if N ** d <= 5000:
         Vo, Uo, _, _ = orc.step(g, V, U)
     else:  # sampled outputs
-        idx = np.arange(256, dtype=np.uint64)
+        idx = np.arange(256 if d < 4 else 96, dtype=np.uint64)
         pl = (W.uniform(5, 1, idx) * d).astype(int)
         nd = (W.uniform(5, 2, idx) * N ** d).astype(int)
         Vs, Us = orc.step_sample(g, V, U, pl, nd)
