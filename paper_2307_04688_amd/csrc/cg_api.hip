@@ -53,7 +53,7 @@ int check_device()
 }
 
 struct Layout {
-    size_t gc, st, V, U, coef, tmp, Bp, W, total;
+    size_t gc, st, V, U, coef, tmp, Bp, W, Bp32, E, G, total;
 };
 
 int validate(const cg_game_desc *g, int precision)
@@ -103,7 +103,6 @@ Layout layout(const cg_game_desc *g, int precision)
     int N4, NC, K;
     long long NN;
     dims(g, N4, NC, K, NN);
-    (void)precision;
     Layout L;
     size_t o = 0;
     L.gc = o; o = align256(o + sizeof(GameConst));
@@ -114,6 +113,12 @@ Layout layout(const cg_game_desc *g, int precision)
     L.tmp = o; o = align256(o + sizeof(double) * g->d * NN);
     L.Bp = o; o = align256(o + sizeof(double) * (size_t)g->d * K * NC);
     L.W = o; o = align256(o + sizeof(double) * (size_t)g->d * NN * NC);
+    L.Bp32 = L.E = L.G = 0;
+    if (precision == CG_FP32_CORR) {
+        L.Bp32 = o; o = align256(o + sizeof(float) * (size_t)g->d * K * NC);
+        L.E = o; o = align256(o + sizeof(double) * (size_t)g->d * g->d * (NN / g->n_nodes) * NC);
+        L.G = o; o = align256(o + sizeof(double) * (size_t)g->d * NN);
+    }
     L.total = o;
     return L;
 }
@@ -135,6 +140,27 @@ void dct1_matrix(int N, double *D)
             if (k == 0 || k == n) v *= 0.5;
             D[l * kMaxN + k] = v * ((l == 0 || l == n) ? 1.0 : 2.0) / (double)n;
         }
+}
+
+// Nodal differentiation matrix: Dd[j][k] = sum_m T_m'(x_j) Dx[m][k], the
+// derivative at node j of the interpolant of values at the nodes.  T_m' by
+// the recurrence T'_{m+1} = 2 T_m + 2 x T'_m - T'_{m-1}.
+void diff_matrix(int N, const double *Dx, const double *x, double *Dd)
+{
+    for (int j = 0; j < N; ++j) {
+        double T[kMaxN], Tp[kMaxN];
+        T[0] = 1.0; Tp[0] = 0.0;
+        if (N > 1) { T[1] = x[j]; Tp[1] = 1.0; }
+        for (int m = 1; m + 1 < N; ++m) {
+            T[m + 1] = 2.0 * x[j] * T[m] - T[m - 1];
+            Tp[m + 1] = 2.0 * T[m] + 2.0 * x[j] * Tp[m] - Tp[m - 1];
+        }
+        for (int k = 0; k < N; ++k) {
+            double s = 0.0;
+            for (int m = 0; m < N; ++m) s += Tp[m] * Dx[m * kMaxN + k];
+            Dd[j * kMaxN + k] = s;
+        }
+    }
 }
 
 }  // namespace
@@ -322,6 +348,7 @@ int cg_init_game(const cg_game_desc *g, int precision, void *ws_dev, size_t ws_b
     for (int m = 0; m < Nu; ++m) hc.unode[m] = 0.5 * g->u_max * (cos_pi_frac(m, Nu - 1) + 1.0);
     dct1_matrix(Nu, hc.Du);
     dct1_matrix(N, hc.Dx);
+    diff_matrix(N, hc.Dx, hc.xnode, hc.Dd);
 
     G->L = L;
     G->ws = (char *)ws_dev;
@@ -337,8 +364,9 @@ int cg_init_game(const cg_game_desc *g, int precision, void *ws_dev, size_t ws_b
     b.tmp = (double *)(G->ws + L.tmp);
     b.Bp = (double *)(G->ws + L.Bp);
     b.W = (double *)(G->ws + L.W);
-    b.Bp32 = nullptr;
-    b.E = nullptr;
+    b.Bp32 = precision == CG_FP32_CORR ? (float *)(G->ws + L.Bp32) : nullptr;
+    b.E = precision == CG_FP32_CORR ? (double *)(G->ws + L.E) : nullptr;
+    b.G = precision == CG_FP32_CORR ? (double *)(G->ws + L.G) : nullptr;
     b.precision = precision;
     b.ev_begin = b.ev_end = nullptr;
     G->prof = false;
@@ -351,6 +379,17 @@ int cg_init_game(const cg_game_desc *g, int precision, void *ws_dev, size_t ws_b
     }
     if (e == hipSuccess) {
         hipLaunchKernelGGL(k_zero, dim3(256), dim3(256), 0, G->stream, b.Bp, (long long)hc.d * hc.K * hc.NC);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess && b.Bp32) {
+        // binary32 operand: zero it through a double view (its size is a multiple of 2 floats)
+        hipLaunchKernelGGL(k_zero, dim3(256), dim3(256), 0, G->stream, (double *)b.Bp32,
+                           (long long)hc.d * hc.K * hc.NC / 2);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess && b.E) {
+        hipLaunchKernelGGL(k_zero, dim3(256), dim3(256), 0, G->stream, b.E,
+                           (long long)hc.d * hc.d * (hc.NN / hc.N) * hc.NC);
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipStreamSynchronize(G->stream);  // hc must outlive the copy

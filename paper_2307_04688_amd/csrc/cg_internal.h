@@ -32,6 +32,8 @@ struct GameConst {
     double unode[kMaxN];       // control nodes u_max (cos(pi m / (Nu-1)) + 1) / 2
     double Du[kMaxN * kMaxN];  // DCT-I matrix of the control fit, [l][m]
     double Dx[kMaxN * kMaxN];  // DCT-I matrix of the state transform, [l][k]
+    double Dd[kMaxN * kMaxN];  // nodal differentiation: derivative at node j of the
+                               // interpolant of nodal values, [j][k] (normalised x)
 };
 
 // Per-game device status words.
@@ -66,13 +68,16 @@ struct StepBuffers {
     double *tmp;             // d * NN, transform intermediate
     double *Bp;              // d * K * NC packed operand (FP64)
     double *W;               // d * NN * NC line coefficients (contraction output)
-    float *Bp32;             // d * K * NC packed remainder operand (FP32 path)
-    double *E;               // FP32_CORR: exact value and first-order tensors
+    float *Bp32;             // d * K * NC packed operand in binary32 (FP32_CORR)
+    double *E;               // FP32_CORR: [d][d][N^(d-1)][NC] value / first-order tensors
+    double *G;               // FP32_CORR: [d][N^d] V_i transformed along mode i
     int precision;
     hipEvent_t ev_begin, ev_end;  // recorded around the contraction kernel when non-null
 };
 hipError_t launch_transform_game(const GameConst &hc, const StepBuffers &b, hipStream_t s);
 hipError_t launch_step(const GameConst &hc, const StepBuffers &b, hipStream_t s);
+hipError_t launch_taylor(const GameConst &hc, const StepBuffers &b, hipStream_t s);
+hipError_t launch_contract_corr(const GameConst &hc, const StepBuffers &b, hipStream_t s);
 
 hipError_t launch_eval(int d, const int *n, const double *coef, const double *x, long long npts,
                        void *out, int precision, void *ws, size_t ws_bytes, hipStream_t s);

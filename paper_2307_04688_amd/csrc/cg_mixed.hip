@@ -1,0 +1,388 @@
+// cg_mixed.hip -- contraction of the value-iteration step with binary32 MFMA
+// and an FP64 correction (precision CG_FP32_CORR).
+//
+// For player i and node j with other-mode coordinates x_l = xbar_l + Delta_l
+// (xbar_l the node, Delta_l = 2 h b_l / p_max the Euler shift), the line
+// coefficients w[j][k_i] = sum_K KR_K(x) c_i[K] split exactly into
+//   w = E0 + sum_l Delta_l E1_l + R,
+//   E0  = sum_K KR_K(xbar) c_i[K]          (V_i transformed along mode i only),
+//   E1_l = sum_K d/dx_l KR_K(xbar) c_i[K]  (the same, differentiated along l),
+//   R   = sum_K A2_K c_i[K],  A2 = KR(x) - KR(xbar) - sum_l Delta_l d/dx_l KR(xbar).
+// E0 and E1 are small FP64 mode products of V (no point evaluation), computed
+// once per iteration; only the second-order remainder R, of relative size
+// ~Delta^2, runs on binary32 MFMA (inputs rounded to binary32, products
+// accumulated in binary32 over N4 K-rows, then added into FP64).
+//
+// A2 is built per K element from per-mode quantities: with T = T_k(x),
+// Tb = T_k(xbar), P = T_k'(xbar) Delta (first-order increment) and
+// R1 = T - Tb - P, a product over a mode set S extends by a mode c as
+//   Rem_{S+c} = Rem_S T_c + Lin_S R1_c + FO_S P_c,
+//   FO_{S+c}  = FO_S Tb_c + Pb_S P_c,   Pb_{S+c} = Pb_S Tb_c,
+//   Lin_S = Pb_S + FO_S,
+// where Pb_S is the product of Tb and FO_S its first-order part, so each
+// K element costs three multiply-adds once the outer modes are combined.
+#include "cg_line.h"
+
+namespace cg {
+
+// G[i] = V_i transformed (DCT-I) along mode i only.
+__global__ __launch_bounds__(256) void k_taylor_a(const GameConst *__restrict__ gc, const GameStatus *st,
+                                                  const double *Vbuf, double *G)
+{
+    __shared__ double Dm[kMaxN * (kMaxN + 1)];
+    if (st->converged) return;
+    const int N = gc->N, d = gc->d;
+    constexpr int LD = kMaxN + 1;
+    for (int e = threadIdx.x; e < N * N; e += blockDim.x) Dm[(e / N) * LD + e % N] = gc->Dx[(e / N) * kMaxN + e % N];
+    __syncthreads();
+    const int NN = (int)gc->NN;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= d * NN) return;
+    const int i = t / NN, idx = t % NN;
+    int stride = 1;
+    for (int l = i + 1; l < d; ++l) stride *= N;
+    const int lo = (idx / stride) % N;
+    const double *src = Vbuf + (long long)st->cur * d * NN + (long long)i * NN + (idx - lo * stride);
+    double acc = 0.0;
+    for (int k = 0; k < N; ++k) acc = fma(Dm[lo * LD + k], src[(long long)k * stride], acc);
+    G[t] = acc;
+}
+
+// E[i][slot][jm][col]: slot 0 = G_i at (jm, col), slot 1 + s = G_i
+// differentiated at the nodes along mode om_s (the s-th mode other than i).
+// jm enumerates the modes other than i in increasing order; col = k_i.
+__global__ __launch_bounds__(256) void k_taylor_b(const GameConst *__restrict__ gc, const GameStatus *st,
+                                                  const double *__restrict__ G, double *E)
+{
+    __shared__ double Dm[kMaxN * (kMaxN + 1)];
+    if (st->converged) return;
+    const int N = gc->N, d = gc->d, NC = gc->NC;
+    constexpr int LD = kMaxN + 1;
+    for (int e = threadIdx.x; e < N * N; e += blockDim.x) Dm[(e / N) * LD + e % N] = gc->Dd[(e / N) * kMaxN + e % N];
+    __syncthreads();
+    const int NN = (int)gc->NN, NM = NN / N;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= d * d * NN) return;
+    const int col = t % N;
+    const int jm = (t / N) % NM;
+    const int slot = (t / NN) % d;
+    const int i = t / (NN * d);
+    // digits of the modes other than i (increasing order) from jm
+    int dig[kMaxD];
+    {
+        int rem = jm;
+        for (int l = d - 1; l >= 0; --l) {
+            if (l == i) continue;
+            dig[l] = rem % N;
+            rem /= N;
+        }
+        dig[i] = col;
+    }
+    int idx = 0;
+    for (int l = 0; l < d; ++l) idx = idx * N + dig[l];
+    const double *Gi = G + (long long)i * NN;
+    double v;
+    if (slot == 0) {
+        v = Gi[idx];
+    } else {
+        const int l = (slot - 1) < i ? slot - 1 : slot;  // om_{slot-1}
+        int stride = 1;
+        for (int m = l + 1; m < d; ++m) stride *= N;
+        const int jl = dig[l];
+        const double *src = Gi + (idx - jl * stride);
+        v = 0.0;
+        for (int k = 0; k < N; ++k) v = fma(Dm[jl * LD + k], src[k * stride], v);
+    }
+    E[(((long long)i * d + slot) * NM + jm) * NC + col] = v;
+}
+
+hipError_t launch_taylor(const GameConst &hc, const StepBuffers &b, hipStream_t s)
+{
+    const long long na = hc.d * hc.NN, nb = (long long)hc.d * hc.d * hc.NN;
+    hipLaunchKernelGGL(k_taylor_a, dim3((unsigned)((na + 255) / 256)), dim3(256), 0, s, b.gc, b.status, b.V, b.G);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_taylor_b, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, b.gc, b.status, b.G, b.E);
+    return hipGetLastError();
+}
+
+// Per-mode basis quantities at one row: T_k(x), T_k(xbar), T_k'(xbar) by
+// three-term recurrences, advanced one k at a time.
+struct ModeRec {
+    double x, xb, dl;            // shifted coordinate, node, Delta
+    double t0, t1, b0, b1, p0, p1;  // T_{k-1}, T_k at x; same at xbar; T'_{k-1}, T'_k at xbar
+    __device__ void init(double x_, double xb_)
+    {
+        x = x_; xb = xb_; dl = x_ - xb_;
+        t0 = 0.0; t1 = 1.0; b0 = 0.0; b1 = 1.0; p0 = 0.0; p1 = 0.0;  // k = 0
+    }
+    // quantities for the current k: T, Tb, P = T' Delta, R1 = T - Tb - P
+    __device__ void get(double &T, double &Tb, double &P, double &R1) const
+    {
+        T = t1; Tb = b1; P = p1 * dl; R1 = (t1 - b1) - P;
+    }
+    __device__ void advance(int k)  // from k to k + 1
+    {
+        double tn, bn, pn;
+        if (k == 0) { tn = x; bn = xb; pn = 1.0; }
+        else {
+            tn = 2.0 * x * t1 - t0;
+            bn = 2.0 * xb * b1 - b0;
+            pn = 2.0 * b1 + 2.0 * xb * p1 - p0;
+        }
+        t0 = t1; t1 = tn; b0 = b1; b1 = bn; p0 = p1; p1 = pn;
+    }
+};
+
+template <int D, int N4, int NC, int RB>
+__global__ __launch_bounds__(256) void k_contract_corr(const GameConst *__restrict__ gc, const GameStatus *st,
+                                                       const double *__restrict__ Ubuf,
+                                                       const float *__restrict__ Bp32,
+                                                       const double *__restrict__ E, double *__restrict__ Wout,
+                                                       int blocks_per_player)
+{
+    constexpr int NCB = NC / 16;
+    constexpr int ROWS_W = RB * 16;
+    constexpr int ROWS_B = 4 * ROWS_W;
+    constexpr int LDB = NC == 32 ? 48 : 16;     // slab rows (floats): kq groups on disjoint banks
+    constexpr int SLAB = N4 * LDB;
+    constexpr int SLAB_E4 = N4 * NC / 4;        // float4 elements per slab
+    constexpr int PF = (SLAB_E4 + 255) / 256;
+    __shared__ float lds[2 * SLAB];
+    __shared__ double dls[ROWS_B * (D - 1)];    // Delta of every row, for the epilogue
+
+    if (st->converged) return;
+    const int cur = st->cur;
+    const int NN = (int)gc->NN;
+    const int N = gc->N;
+    const double *Uold = Ubuf + (long long)cur * D * NN;
+
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int r16 = lane & 15, kq = lane >> 4;
+    const int player = blockIdx.x / blocks_per_player;
+    const int tile = blockIdx.x % blocks_per_player;
+    const int row0 = tile * ROWS_B + wave * ROWS_W;
+
+    int om[D - 1];
+#pragma unroll
+    for (int t = 0; t < D - 1; ++t) om[t] = t < player ? t : t + 1;
+
+    // ---- per row: node, shift, inner-mode quantities, outer-mode recurrences ----
+    float Tc[RB][N4 / 4], Rc[RB][N4 / 4], Pc[RB][N4 / 4];
+    ModeRec ra[RB], rb_[RB];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) {
+        const int j = min(row0 + rb * 16 + r16, NN - 1);
+        double p[D], ub[D], b[D];
+        node_state<D>(gc, Uold, j, p, ub, b);
+        int dig[D];
+        {
+            int rem = j;
+#pragma unroll
+            for (int l = D - 1; l >= 0; --l) { dig[l] = rem % N; rem /= N; }
+        }
+        double xs[D - 1], xb[D - 1];
+#pragma unroll
+        for (int t = 0; t < D - 1; ++t) {
+            double y = 0.0, xbar = 0.0;
+#pragma unroll
+            for (int l = 0; l < D; ++l)
+                if (l == om[t]) { y = fma(gc->h, b[l], p[l]); xbar = gc->xnode[dig[l]]; }
+            xs[t] = 2.0 * y / gc->pmax - 1.0;
+            xb[t] = xbar;
+            if (kq == 0) dls[(wave * ROWS_W + rb * 16 + r16) * (D - 1) + t] = xs[t] - xbar;
+        }
+        ModeRec rc;
+        rc.init(xs[D - 2], xb[D - 2]);
+#pragma unroll
+        for (int k = 0; k < N4; ++k) {
+            if ((k & 3) == kq) {
+                double T, Tb, P, R1;
+                rc.get(T, Tb, P, R1);
+                Tc[rb][k >> 2] = (float)T;
+                Rc[rb][k >> 2] = (float)R1;
+                Pc[rb][k >> 2] = (float)P;
+            }
+            rc.advance(k);
+        }
+        if (D >= 3) ra[rb].init(xs[0], xb[0]);
+        if (D >= 4) rb_[rb].init(xs[1], xb[1]);
+    }
+
+    f32x4 acc[RB][NCB];
+    double acc64[RB][NCB][4];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int c = 0; c < NCB; ++c) {
+            acc[rb][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc64[rb][c][v] = 0.0;
+        }
+
+    const float4 *Bg = reinterpret_cast<const float4 *>(Bp32 + (long long)player * gc->K * NC);
+    float4 pf[PF];
+    auto load_slab = [&](int oc) {
+#pragma unroll
+        for (int q = 0; q < PF; ++q) {
+            const int e4 = tid + q * 256;
+            if (e4 < SLAB_E4) pf[q] = Bg[(long long)oc * SLAB_E4 + e4];
+        }
+    };
+    auto store_slab = [&](float *buf) {
+#pragma unroll
+        for (int q = 0; q < PF; ++q) {
+            const int e4 = tid + q * 256;
+            if (e4 < SLAB_E4) {
+                const int e = 4 * e4, r = e / NC, c = e % NC;
+                float *dst = buf + r * LDB + c;
+                dst[0] = pf[q].x; dst[1] = pf[q].y; dst[2] = pf[q].z; dst[3] = pf[q].w;
+            }
+        }
+    };
+
+    const int n_outer = (D == 2) ? 1 : (D == 3 ? N : N * N);
+    load_slab(0);
+    store_slab(lds);
+    __syncthreads();
+    for (int oc = 0; oc < n_outer; ++oc) {
+        const float *cb = lds + (oc & 1) * SLAB;
+        const bool more = oc + 1 < n_outer;
+        if (more) load_slab(oc + 1);
+        // outer-mode factors of the remainder recursion
+        float fRem[RB], fLin[RB], fFO[RB];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+            if (D == 2) {
+                fRem[rb] = 0.f; fLin[rb] = 1.f; fFO[rb] = 0.f;
+            } else {
+                double Ta, Tba, Pa, R1a;
+                ra[rb].get(Ta, Tba, Pa, R1a);
+                double Rem = R1a, FO = Pa, Pb = Tba;
+                if (D == 4) {
+                    double Tb, Tbb, Pb2, R1b;
+                    rb_[rb].get(Tb, Tbb, Pb2, R1b);
+                    const double Lin = Pb + FO;
+                    Rem = Rem * Tb + Lin * R1b + FO * Pb2;
+                    FO = FO * Tbb + Pb * Pb2;
+                    Pb = Pb * Tbb;
+                }
+                fRem[rb] = (float)Rem;
+                fLin[rb] = (float)(Pb + FO);
+                fFO[rb] = (float)FO;
+            }
+        }
+        // all B fragments of the slab first, so the LDS latency is paid once
+        float bf[N4 / 4][NCB];
+#pragma unroll
+        for (int t = 0; t < N4 / 4; ++t)
+#pragma unroll
+            for (int c = 0; c < NCB; ++c) bf[t][c] = cb[(4 * t + kq) * LDB + c * 16 + r16];
+#pragma unroll
+        for (int t = 0; t < N4 / 4; ++t) {
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) {
+                const float a = fmaf(fRem[rb], Tc[rb][t], fmaf(fLin[rb], Rc[rb][t], fFO[rb] * Pc[rb][t]));
+#pragma unroll
+                for (int c = 0; c < NCB; ++c)
+                    acc[rb][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bf[t][c], acc[rb][c], 0, 0, 0);
+            }
+        }
+        // binary32 partial sums of this slab into FP64
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int c = 0; c < NCB; ++c) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc64[rb][c][v] += (double)acc[rb][c][v];
+                acc[rb][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+            }
+        // advance the outer-mode recurrences
+        if (D == 3) {
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) ra[rb].advance(oc);
+        } else if (D == 4) {
+            const int kb = oc % N;
+            if (kb == N - 1) {
+                const int ka = oc / N;
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb) {
+                    ra[rb].advance(ka);
+                    rb_[rb].init(rb_[rb].x, rb_[rb].xb);
+                }
+            } else {
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb) rb_[rb].advance(kb);
+            }
+        }
+        if (more) store_slab(lds + ((oc + 1) & 1) * SLAB);
+        __syncthreads();
+    }
+
+    // ---- epilogue: element v of lane c + 16 kq is row 4 kq + v (f32 layout) ----
+    const int NM = NN / N;
+    int stride_i = 1;
+    for (int l = player + 1; l < D; ++l) stride_i *= N;
+    const double *Ei = E + (long long)player * D * NM * NC;
+    double *Wp = Wout + (long long)player * NN * NC;
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int rl = rb * 16 + 4 * kq + v;
+            const int j = row0 + rl;
+            if (j >= NN) continue;
+            // node index without mode i
+            const int hi = j / (stride_i * N), lo = j % stride_i;
+            const int jm = hi * stride_i + lo;
+            const double *dl = dls + (wave * ROWS_W + rl) * (D - 1);
+#pragma unroll
+            for (int c = 0; c < NCB; ++c) {
+                const int col = c * 16 + r16;
+                double w = acc64[rb][c][v] + Ei[(long long)jm * NC + col];
+#pragma unroll
+                for (int t = 0; t < D - 1; ++t) w = fma(dl[t], Ei[((long long)(1 + t) * NM + jm) * NC + col], w);
+                Wp[(long long)j * NC + col] = w;
+            }
+        }
+}
+
+template <int D, int N4>
+static hipError_t launch_corr_dn(const GameConst &hc, const StepBuffers &b, hipStream_t s)
+{
+    constexpr int NC = N4 <= 16 ? 16 : 32;
+    constexpr int RB = 2;
+    const int NN = (int)hc.NN;
+    const int bpp = (NN + 4 * RB * 16 - 1) / (4 * RB * 16);
+    hipLaunchKernelGGL((k_contract_corr<D, N4, NC, RB>), dim3(bpp * D), dim3(256), 0, s, b.gc, b.status, b.U,
+                       b.Bp32, b.E, b.W, bpp);
+    return hipGetLastError();
+}
+
+template <int D>
+static hipError_t launch_corr_d(const GameConst &hc, const StepBuffers &b, hipStream_t s)
+{
+    switch (hc.N4) {
+        case 4: return launch_corr_dn<D, 4>(hc, b, s);
+        case 8: return launch_corr_dn<D, 8>(hc, b, s);
+        case 12: return launch_corr_dn<D, 12>(hc, b, s);
+        case 16: return launch_corr_dn<D, 16>(hc, b, s);
+        case 20: return launch_corr_dn<D, 20>(hc, b, s);
+        case 24: return launch_corr_dn<D, 24>(hc, b, s);
+        case 28: return launch_corr_dn<D, 28>(hc, b, s);
+        case 32: return launch_corr_dn<D, 32>(hc, b, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_contract_corr(const GameConst &hc, const StepBuffers &b, hipStream_t s)
+{
+    switch (hc.d) {
+        case 2: return launch_corr_d<2>(hc, b, s);
+        case 3: return launch_corr_d<3>(hc, b, s);
+        case 4: return launch_corr_d<4>(hc, b, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace cg

@@ -132,17 +132,22 @@ __global__ __launch_bounds__(256) void k_contract_f64(const GameConst *__restric
         double F[RB];
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) F[rb] = (D == 2) ? 1.0 : (D == 3 ? Ta[rb] : Ta[rb] * Tb[rb]);
+        // B fragments one K-step ahead of the MFMAs that use them
+        double bf[2][NCB];
+#pragma unroll
+        for (int c = 0; c < NCB; ++c) bf[0][c] = cb[kq * LDB + c * 16 + r16];
 #pragma unroll
         for (int t = 0; t < N4 / 4; ++t) {
-            double bf[NCB];
+            if (t + 1 < N4 / 4) {
 #pragma unroll
-            for (int c = 0; c < NCB; ++c) bf[c] = cb[(4 * t + kq) * LDB + c * 16 + r16];
+                for (int c = 0; c < NCB; ++c) bf[(t + 1) & 1][c] = cb[(4 * (t + 1) + kq) * LDB + c * 16 + r16];
+            }
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb) {
                 const double a = F[rb] * Tl[rb][t];
 #pragma unroll
                 for (int c = 0; c < NCB; ++c)
-                    acc[rb][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bf[c], acc[rb][c], 0, 0, 0);
+                    acc[rb][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bf[t & 1][c], acc[rb][c], 0, 0, 0);
             }
         }
         // advance the outer-mode recurrences T_{k+1} = 2 x T_k - T_{k-1}
@@ -307,13 +312,22 @@ static hipError_t launch_step_dn(const GameConst &hc, const StepBuffers &b, hipS
     constexpr int RB = 2;  // 32 rows per wave
     const int NN = (int)hc.NN;
     const int bpp = (NN + 4 * RB * 16 - 1) / (4 * RB * 16);
-    if (b.ev_begin) {
-        hipError_t e = hipEventRecord(b.ev_begin, s);
+    hipError_t e;
+    if (b.precision == CG_FP32_CORR) {
+        e = launch_taylor(hc, b, s);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((k_contract_f64<D, N4, NC, RB>), dim3(bpp * D), dim3(256), 0, s, b.gc, b.status, b.U, b.Bp,
-                       b.W, bpp);
-    hipError_t e = hipGetLastError();
+    if (b.ev_begin) {
+        e = hipEventRecord(b.ev_begin, s);
+        if (e != hipSuccess) return e;
+    }
+    if (b.precision == CG_FP32_CORR) {
+        e = launch_contract_corr(hc, b, s);
+    } else {
+        hipLaunchKernelGGL((k_contract_f64<D, N4, NC, RB>), dim3(bpp * D), dim3(256), 0, s, b.gc, b.status, b.U,
+                           b.Bp, b.W, bpp);
+        e = hipGetLastError();
+    }
     if (e != hipSuccess) return e;
     if (b.ev_end) {
         e = hipEventRecord(b.ev_end, s);

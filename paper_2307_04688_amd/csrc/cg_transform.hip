@@ -95,7 +95,7 @@ __device__ __forceinline__ long long packed_index(const GameConst *__restrict__ 
 }
 
 __global__ __launch_bounds__(256) void k_tf_fast(const GameConst *__restrict__ gc, const GameStatus *st,
-                                                 const double *Vbuf, double *out, double *Bp)
+                                                 const double *Vbuf, double *out, double *Bp, float *Bp32)
 {
     constexpr int LD = kMaxN + 1;  // odd stride: column reads hit distinct banks
     __shared__ double Dm[kMaxN * LD];
@@ -156,7 +156,8 @@ __global__ __launch_bounds__(256) void k_tf_fast(const GameConst *__restrict__ g
                 out[(long long)i * NN + (long long)sl * NN2 + e] = acc[u];
             } else {
                 int dig[kMaxD] = {rrow[u], lcol[u], 0, 0};
-                Bp[packed_index(gc, i, dig)] = acc[u];
+                const long long o = packed_index(gc, i, dig);
+                if (Bp32) Bp32[o] = (float)acc[u]; else Bp[o] = acc[u];
             }
         }
     }
@@ -165,7 +166,7 @@ __global__ __launch_bounds__(256) void k_tf_fast(const GameConst *__restrict__ g
 // Tile of the outer modes: X[f][q], f over the N^(d-2) outer positions,
 // q over Q consecutive inner positions (the two fast modes flattened).
 __global__ __launch_bounds__(256) void k_tf_outer(const GameConst *__restrict__ gc, const GameStatus *st,
-                                                  const double *__restrict__ in, double *Bp, int Q)
+                                                  const double *__restrict__ in, double *Bp, float *Bp32, int Q)
 {
     extern __shared__ double sh[];
     if (st->converged) return;
@@ -192,7 +193,8 @@ __global__ __launch_bounds__(256) void k_tf_outer(const GameConst *__restrict__ 
             double acc = 0.0;
             for (int k = 0; k < N; ++k) acc = fma(Dm[l * LD + k], X[k * Q + qq], acc);
             int dig[kMaxD] = {l, q / N, q % N, 0};
-            Bp[packed_index(gc, i, dig)] = acc;
+            const long long o = packed_index(gc, i, dig);
+            if (Bp32) Bp32[o] = (float)acc; else Bp[o] = acc;
         }
     } else {  // d == 4: mode 0 then mode 1; f = a * N + b
         for (int e = threadIdx.x; e < F * Q; e += blockDim.x) {
@@ -208,7 +210,8 @@ __global__ __launch_bounds__(256) void k_tf_outer(const GameConst *__restrict__ 
             double acc = 0.0;
             for (int k = 0; k < N; ++k) acc = fma(Dm[lb * LD + k], Y[(a * N + k) * Q + qq], acc);
             int dig[kMaxD] = {a, lb, q / N, q % N};
-            Bp[packed_index(gc, i, dig)] = acc;
+            const long long o = packed_index(gc, i, dig);
+            if (Bp32) Bp32[o] = (float)acc; else Bp[o] = acc;
         }
     }
 }
@@ -217,7 +220,9 @@ hipError_t launch_transform_game(const GameConst &hc, const StepBuffers &b, hipS
 {
     const int N = hc.N, d = hc.d;
     const long long nslice = hc.NN / (N * N);
-    hipLaunchKernelGGL(k_tf_fast, dim3((unsigned)(nslice * d)), dim3(256), 0, s, b.gc, b.status, b.V, b.tmp, b.Bp);
+    float *Bp32 = b.precision == CG_FP32_CORR ? b.Bp32 : nullptr;  // packed operand in binary32
+    hipLaunchKernelGGL(k_tf_fast, dim3((unsigned)(nslice * d)), dim3(256), 0, s, b.gc, b.status, b.V, b.tmp, b.Bp,
+                       Bp32);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || d == 2) return e;
     // Q inner positions per tile, so that the dynamic LDS (D plus one or two
@@ -228,7 +233,8 @@ hipError_t launch_transform_game(const GameConst &hc, const StepBuffers &b, hipS
     Q = Q > 16 ? 16 : (Q < 1 ? 1 : Q);
     const size_t shmem = sizeof(double) * ((size_t)kMaxN * (kMaxN + 1) + (size_t)tiles * F * Q);
     const int nq = (N * N + Q - 1) / Q;
-    hipLaunchKernelGGL(k_tf_outer, dim3((unsigned)(nq * d)), dim3(256), shmem, s, b.gc, b.status, b.tmp, b.Bp, Q);
+    hipLaunchKernelGGL(k_tf_outer, dim3((unsigned)(nq * d)), dim3(256), shmem, s, b.gc, b.status, b.tmp, b.Bp, Bp32,
+                       Q);
     return hipGetLastError();
 }
 

@@ -1,0 +1,161 @@
+"""Mixed-precision path (CG_FP32_CORR) against the FP64 oracle.
+
+Targets: 1e-8 normwise relative on V against the oracle over whole solves;
+for one step, the a-priori bound of the binary32 remainder contraction
+(see test_one_step_within_a_priori_bound).
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+from numpy.polynomial import chebyshev as npc
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def cg():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2307_04688_amd import chebgame
+    chebgame.lib()
+    return chebgame
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def test_c2_workload_mixed_against_oracle_reference(cg):
+    ref = json.load(open(os.path.join(GOLD, "c2_oracle_reference.json")))
+    g = W.config_game("C2")
+    say("mixed C2 200 steps vs reference")
+    G = cg.ChebGame(g, cg.FP32_CORR)
+    pl, nd = np.array(ref["players"]), np.array(ref["nodes"])
+    done = 0
+    for s in sorted(int(k) for k in ref["snapshots"]):
+        G.step(s - done)
+        done = s
+        V, U, _ = G.get_state()
+        V, U = V.cpu().numpy(), U.cpu().numpy()
+        snap = ref["snapshots"][str(s)]
+        ev = np.max(np.abs(V[pl, nd] - np.array(snap["V"]))) / ref["vmax"][s - 1]
+        eu = np.max(np.abs(U[pl, nd] - np.array(snap["U"]))) / g.u_max
+        say(f"  step {s}: rel V {ev:.2e}  u {eu:.2e}")
+        assert ev <= 1e-8 and eu <= 1e-8, s
+
+
+@pytest.mark.parametrize("d,N,steps", [(2, 9, 30), (3, 10, 30), (4, 6, 20), (2, 32, 40), (3, 16, 20)])
+def test_mixed_every_step_small_games(cg, orc, d, N, steps):
+    g = W.make_game(d, N, seed=3 + N, per_player=True)
+    G = cg.ChebGame(g, cg.FP32_CORR)
+    Vo, Uo = orc.zero_state(g)
+    worst = 0.0
+    for r in range(steps):
+        Vo, Uo, _, _ = orc.step(g, Vo, Uo)
+        G.step(1)
+        V, U, _ = G.get_state()
+        e = np.max(np.abs(V.cpu().numpy() - Vo)) / np.max(np.abs(Vo))
+        worst = max(worst, e)
+        assert e <= 1e-9, r
+        assert np.max(np.abs(U.cpu().numpy() - Uo)) <= 1e-8 * g.u_max, r
+    say(f"  d={d} N={N}: worst rel V over {steps} steps {worst:.2e}")
+
+
+def _basis(n, x):
+    """T_0..T_{n-1}(x) and T_k'(x) for scalar x (numpy chebyshev)."""
+    V = npc.chebvander(np.array([x]), n - 1)[0]
+    D = np.array([npc.chebval(x, npc.chebder(np.eye(n)[k])) if k > 0 else 0.0 for k in range(n)])
+    return V, D
+
+
+def test_one_step_within_a_priori_bound(cg, orc):
+    """One mixed step from a smooth state (the oracle's iterate after 12
+    steps) against the oracle's step, per sampled (player, node), within
+
+        |dV| <= delta * sum_{k_i} max_line |T_{k_i}| * |dw_{k_i}|,
+        |dw_{k_i}| <= (8 u + gamma_{N4}(u)) * sum_K S_K |c[K, k_i]|   (u = 2^-24),
+        S = |R1_a T_c| + |(Tb_a + P_a) R1_c| + |P_a P_c|,
+
+    where A2 = R1_a T_c + (Tb_a + P_a) R1_c + P_a P_c is the second-order
+    remainder of the Khatri-Rao basis at the shifted point, the only part
+    contracted in binary32: six binary32 factors and c each rounded once, three
+    rounded operations to form an element (the terms may cancel, hence S),
+    products accumulated over N4 K-rows in binary32 and then in FP64.  A2 and
+    the coefficients come from numpy and the oracle.  The FP64 rest of the
+    step adds its own budget, 1e-13 max|V|."""
+    g = W.make_game(3, 12, seed=9, per_player=True)
+    V, U, _ = orc.solve(g, 12)
+    Vo, Uo, _, _ = orc.step(g, V, U)
+    G = cg.ChebGame(g, cg.FP32_CORR)
+    G.set_state(dev(V), dev(U))
+    G.step(1)
+    Vg = G.get_state()[0].cpu().numpy()
+    N, d = g.N, g.d
+    x1 = orc.nodes(N)
+    p1 = 0.5 * g.p_max * (x1 + 1)
+    M = np.asarray(g.K) / np.asarray(g.m)[:, None] - np.diag(g.c)
+    delta = 1 - g.rho * g.h
+    u32 = 2.0 ** -24
+    N4 = (N + 3) // 4 * 4
+    factor = 8 * u32 + N4 * u32 / (1 - N4 * u32)
+    idx = np.arange(48, dtype=np.uint64)
+    players = (W.uniform(9, 3, idx) * d).astype(int)
+    nodes = (W.uniform(9, 4, idx) * N ** d).astype(int)
+    worst_ratio = 0.0
+    for i, j in zip(players, nodes):
+        coef = orc.transform(V[i].reshape((N,) * d))
+        kk = np.unravel_index(j, (N,) * d)
+        p = p1[list(kk)]
+        b = M @ p + np.asarray(g.beta) * U[:, j]
+        x = 2 * (p + g.h * b) / g.p_max - 1
+        xb = x1[list(kk)]
+        others = [l for l in range(d) if l != i]
+        T, Tb, P, R1 = {}, {}, {}, {}
+        for l in others:
+            T[l] = _basis(N, x[l])[0]
+            Tb[l], Dl = _basis(N, xb[l])
+            P[l] = Dl * (x[l] - xb[l])
+            R1[l] = T[l] - Tb[l] - P[l]
+        a, c = others
+        S = (np.abs(np.outer(R1[a], T[c])) + np.abs(np.outer(Tb[a] + P[a], R1[c]))
+             + np.abs(np.outer(P[a], P[c])))
+        cm = np.moveaxis(coef, i, -1)                     # [k_a, k_c, k_i]
+        dw = factor * np.einsum("ac,aci->i", S, np.abs(cm))
+        # line points: x_i over the control range
+        xi = 2 * (p[i] + g.h * (b[i] + g.beta[i] * (np.array([0.0, g.u_max]) - U[i, j]))) / g.p_max - 1
+        Tmax = np.maximum(np.abs(npc.chebvander(xi, N - 1)).max(axis=0), 1.0)
+        # binary32 share plus the FP64 share (the FP64 path's own bar)
+        bound = delta * np.sum(Tmax * dw) + 1e-13 * np.max(np.abs(Vo))
+        err = abs(Vg[i, j] - Vo[i, j])
+        worst_ratio = max(worst_ratio, err / bound)
+        assert err <= bound, (i, j, err, bound)
+    say(f"  worst measured/bound {worst_ratio:.2e}")
+
+
+def test_mixed_checkpoint_and_symmetry(cg):
+    g = W.make_game(3, 12, seed=5, nominal=True)
+    A = cg.ChebGame(g, cg.FP32_CORR)
+    A.step(12)
+    Va, Ua, _ = A.get_state()
+    B = cg.ChebGame(g, cg.FP32_CORR)
+    B.step(6)
+    Vm, Um, _ = B.get_state()
+    C = cg.ChebGame(g, cg.FP32_CORR)
+    C.set_state(Vm, Um)
+    C.step(6)
+    Vc, Uc, _ = C.get_state()
+    assert torch.equal(Va, Vc) and torch.equal(Ua, Uc)
+    Vn = Va.cpu().numpy().reshape(3, 12, 12, 12)
+    assert np.max(np.abs(Vn[0] - np.transpose(Vn[2], (2, 1, 0)))) <= 1e-10 * np.max(np.abs(Vn))
