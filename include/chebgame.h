@@ -160,6 +160,41 @@ int cg_solve(cg_game *game, int32_t max_steps, double tol, int32_t *steps_done, 
 int cg_get_state(cg_game *game, double *V_dev, double *U_dev, int32_t *r);
 int cg_set_state(cg_game *game, const double *V_dev, const double *U_dev);
 
+/* Batched value iteration: many games, of uneven d, N and parameters,
+ * advanced together.  Games with the same d, N, precision and control-fit
+ * path form a group; one iteration of every group is a fixed sequence of
+ * kernel launches, each covering all games of its group (blocks are mapped
+ * to (game, player, node tile) through a device table).  That sequence is
+ * captured once in a hipGraph and replayed per iteration.  Each game keeps
+ * its own state, status and convergence test (Step 4): a converged game's
+ * blocks return at once.
+ *
+ * cg_batch_create: 'games' (count >= 1 distinct, initialised handles; host
+ * array, copied) must stay valid and must not be used on other streams while
+ * the batch works; ws_dev (>= cg_batch_workspace_bytes(count), 256-byte
+ * aligned, device) holds the device tables; work is queued on 'stream'.
+ * cg_batch_autotune: for every group, times the contraction's row blocking
+ * (16, 32 or 64 nodes per wave) over 'trial_steps' iterations and keeps the
+ * fastest; it resets every game of the batch to V = 0, u = A.  Synchronises.
+ * cg_batch_solve: like cg_solve for every game at once; steps_done and
+ * residuals (host arrays of count entries, nullable) receive each game's
+ * iteration count and last residual.  Synchronises.  Returns
+ * CG_ENOTCONVERGED if tol > 0 and some game did not reach it, CG_ENONFINITE
+ * if some game produced a non-finite value: that game stopped at that
+ * iteration, its residuals entry is non-finite, and every other game ran on
+ * unaffected (its entries are valid).
+ * cg_batch_groups: number of groups and, if rb is not NULL, the row blocking
+ * chosen per group (host array of CG_MAX_GROUPS entries). */
+#define CG_MAX_GROUPS 64
+typedef struct cg_batch cg_batch;
+size_t cg_batch_workspace_bytes(int32_t count);
+int cg_batch_create(cg_game *const *games, int32_t count, void *ws_dev, size_t ws_bytes, void *stream,
+                    cg_batch **out);
+int cg_batch_autotune(cg_batch *batch, int32_t trial_steps);
+int cg_batch_solve(cg_batch *batch, int32_t max_steps, double tol, int32_t *steps_done, double *residuals);
+int cg_batch_groups(cg_batch *batch, int32_t *rb);
+int cg_batch_destroy(cg_batch *batch);
+
 /* Timing of the contraction kernel (the fused step kernel that carries the
  * mode-n contractions).  With enable != 0, every later step records a pair of
  * HIP events on the game's stream around that kernel's launch.  If kernel_ms

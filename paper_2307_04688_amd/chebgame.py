@@ -69,6 +69,13 @@ def lib() -> C.CDLL:
     L.cg_get_state.argtypes = [vp, vp, vp, ip]
     L.cg_set_state.argtypes = [vp, vp, vp]
     L.cg_profile.argtypes = [vp, C.c_int, dp, C.POINTER(C.c_int64)]
+    L.cg_batch_workspace_bytes.restype = C.c_size_t
+    L.cg_batch_workspace_bytes.argtypes = [C.c_int32]
+    L.cg_batch_create.argtypes = [C.POINTER(vp), C.c_int32, vp, C.c_size_t, vp, C.POINTER(vp)]
+    L.cg_batch_autotune.argtypes = [vp, C.c_int32]
+    L.cg_batch_solve.argtypes = [vp, C.c_int32, C.c_double, ip, dp]
+    L.cg_batch_groups.argtypes = [vp, ip]
+    L.cg_batch_destroy.argtypes = [vp]
     _lib = L
     return L
 
@@ -188,6 +195,66 @@ class ChebGame:
             pass
 
 
+class ChebBatch:
+    """A cg_batch* over existing ChebGame handles (which it keeps alive).
+
+    Games with the same d, N, precision and control-fit path share one launch
+    per kernel; one iteration of every group is a captured graph that each
+    solve replays."""
+
+    def __init__(self, games: Sequence[ChebGame], stream=None):
+        import torch
+        if len(games) == 0:
+            raise ChebGameError(EINVAL, "empty batch")
+        self.games = list(games)
+        L = lib()
+        n = len(self.games)
+        nbytes = int(L.cg_batch_workspace_bytes(n))
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        arr = (C.c_void_p * n)(*[g.handle for g in self.games])
+        h = C.c_void_p()
+        _check(L.cg_batch_create(arr, n, C.c_void_p(self.ws.data_ptr()), nbytes, C.c_void_p(_stream(stream)),
+                                 C.byref(h)))
+        self.handle = h
+
+    def autotune(self, trial_steps: int = 3):
+        """Pick the contraction row blocking per group; resets every game to V=0, u=A."""
+        _check(lib().cg_batch_autotune(self.handle, trial_steps))
+        return self.groups()
+
+    def groups(self) -> list:
+        rb = (C.c_int32 * 64)()
+        n = _check(lib().cg_batch_groups(self.handle, rb))
+        return list(rb[:n])
+
+    def solve(self, max_steps: int, tol: float = 0.0):
+        """Returns (status, steps_done[count], last residual[count]).  A game
+        that produced a non-finite value (status ENONFINITE) has a non-finite
+        residual; the other games' entries are valid."""
+        n = len(self.games)
+        steps = (C.c_int32 * n)()
+        res = (C.c_double * n)()
+        rc = lib().cg_batch_solve(self.handle, max_steps, float(tol), steps, res)
+        if rc != ENONFINITE:
+            _check(rc)
+        return rc, np.array(steps[:], dtype=np.int64), np.array(res[:], dtype=np.float64)
+
+    def reset(self):
+        for g in self.games:
+            g.reset()
+
+    def destroy(self):
+        if getattr(self, "handle", None):
+            lib().cg_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
 # Module-level functions named after the C entry points.
 
 def init_game(game, precision: int = FP64, stream=None) -> ChebGame:
@@ -212,6 +279,26 @@ def set_state(g: ChebGame, V, U=None):
 
 def destroy(g: ChebGame):
     g.destroy()
+
+
+def batch_create(games: Sequence[ChebGame], stream=None) -> ChebBatch:
+    return ChebBatch(games, stream)
+
+
+def batch_autotune(b: ChebBatch, trial_steps: int = 3):
+    return b.autotune(trial_steps)
+
+
+def batch_solve(b: ChebBatch, max_steps: int, tol: float = 0.0):
+    return b.solve(max_steps, tol)
+
+
+def batch_groups(b: ChebBatch):
+    return b.groups()
+
+
+def batch_destroy(b: ChebBatch):
+    b.destroy()
 
 
 def chebyshev_transform(vals, d: Optional[int] = None, stream=None):

@@ -53,7 +53,7 @@ int check_device()
 }
 
 struct Layout {
-    size_t gc, st, V, U, coef, tmp, Bp, W, Bp32, E, G, total;
+    size_t gc, st, tab, V, U, coef, tmp, Bp, W, Bp32, E, G, total;
 };
 
 int validate(const cg_game_desc *g, int precision)
@@ -107,6 +107,7 @@ Layout layout(const cg_game_desc *g, int precision)
     size_t o = 0;
     L.gc = o; o = align256(o + sizeof(GameConst));
     L.st = o; o = align256(o + sizeof(GameStatus));
+    L.tab = o; o = align256(o + sizeof(Inst));
     L.V = o; o = align256(o + sizeof(double) * 2 * g->d * NN);
     L.U = o; o = align256(o + sizeof(double) * 2 * g->d * NN);
     L.coef = o; o = align256(o + sizeof(double) * g->d * NN);
@@ -172,6 +173,7 @@ struct cg_game {
     hipStream_t stream;
     int precision;
     StepBuffers b;
+    Inst inst;          // host copy of the one-entry device table
     long long launched; // iterations queued (including no-ops after convergence)
     bool prof;                     // record events around the contraction kernel
     std::vector<hipEvent_t> evs;   // pairs (begin, end), one pair per profiled launch
@@ -181,6 +183,17 @@ struct cg_game {
         for (hipEvent_t e : evs) (void)hipEventDestroy(e);
     }
 };
+
+namespace cg {
+const GameConst &game_consts(const cg_game *g) { return g->hc; }
+const Inst &game_inst(const cg_game *g) { return g->inst; }
+int game_precision(const cg_game *g) { return g->precision; }
+int set_error(int code, const char *msg)
+{
+    g_last_error = msg;
+    return code;
+}
+}  // namespace cg
 
 namespace {
 
@@ -369,10 +382,26 @@ int cg_init_game(const cg_game_desc *g, int precision, void *ws_dev, size_t ws_b
     b.G = precision == CG_FP32_CORR ? (double *)(G->ws + L.G) : nullptr;
     b.precision = precision;
     b.ev_begin = b.ev_end = nullptr;
+    b.tab = (const Inst *)(G->ws + L.tab);
+    b.count = 1;
+    b.rb = 2;
+    Inst &hi = G->inst;
+    hi.gc = b.gc;
+    hi.st = b.status;
+    hi.V = b.V;
+    hi.U = b.U;
+    hi.coef = b.coef;
+    hi.tmp = b.tmp;
+    hi.Bp = b.Bp;
+    hi.W = b.W;
+    hi.Bp32 = b.Bp32;
+    hi.E = b.E;
+    hi.G = b.G;
     G->prof = false;
     G->ev_used = 0;
 
     hipError_t e = hipMemcpyAsync(G->ws + L.gc, &hc, sizeof hc, hipMemcpyHostToDevice, G->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(G->ws + L.tab, &G->inst, sizeof(Inst), hipMemcpyHostToDevice, G->stream);
     if (e == hipSuccess) {
         hipLaunchKernelGGL(k_fill_state, dim3(256), dim3(256), 0, G->stream, b.V, b.U, b.gc, b.status);
         e = hipGetLastError();
@@ -392,7 +421,7 @@ int cg_init_game(const cg_game_desc *g, int precision, void *ws_dev, size_t ws_b
                            (long long)hc.d * hc.d * (hc.NN / hc.N) * hc.NC);
         e = hipGetLastError();
     }
-    if (e == hipSuccess) e = hipStreamSynchronize(G->stream);  // hc must outlive the copy
+    if (e == hipSuccess) e = hipStreamSynchronize(G->stream);  // hc and inst must outlive the copies
     if (e != hipSuccess) {
         delete G;
         return hip_fail(e, "cg_init_game");

@@ -59,6 +59,20 @@ hipError_t launch_transform_mode(const double *in, double *out, int d, const int
 hipError_t run_transform(int d, const int *n, const double *vals, double *coef, long long batch,
                          hipStream_t s);
 
+// Device pointers of one game instance.  Step kernels take a table of
+// these and serve tab[blockIdx.x / blocks_per_instance], so that one launch
+// covers every instance of a group with the same d and N.
+struct Inst {
+    const GameConst *gc;
+    GameStatus *st;
+    double *V, *U;           // [2][d][NN] each
+    double *coef, *tmp;      // transform intermediates
+    double *Bp;              // packed operand (FP64)
+    double *W;               // line coefficients
+    float *Bp32;             // packed operand (binary32, FP32_CORR)
+    double *E, *G;           // FP32_CORR tensors
+};
+
 // One value-iteration step of a game (all kernels of Steps 1-4).
 struct StepBuffers {
     const GameConst *gc;     // device
@@ -73,6 +87,9 @@ struct StepBuffers {
     double *G;               // FP32_CORR: [d][N^d] V_i transformed along mode i
     int precision;
     hipEvent_t ev_begin, ev_end;  // recorded around the contraction kernel when non-null
+    const Inst *tab;              // device table of the instances of this launch
+    int count;                    // instances in the table (same d, N, precision)
+    int rb;                       // rows blocks of 16 per wave in the contraction (1, 2 or 4)
 };
 hipError_t launch_transform_game(const GameConst &hc, const StepBuffers &b, hipStream_t s);
 hipError_t launch_step(const GameConst &hc, const StepBuffers &b, hipStream_t s);
@@ -82,5 +99,12 @@ hipError_t launch_contract_corr(const GameConst &hc, const StepBuffers &b, hipSt
 hipError_t launch_eval(int d, const int *n, const double *coef, const double *x, long long npts,
                        void *out, int precision, void *ws, size_t ws_bytes, hipStream_t s);
 size_t eval_ws_bytes(int d, const int *n, int precision);
+
+// Accessors of a game handle for the batch code (defined with the handle).
+const GameConst &game_consts(const cg_game *g);
+const Inst &game_inst(const cg_game *g);
+int game_precision(const cg_game *g);
+// Records an error message for cg_last_error(); returns code.
+int set_error(int code, const char *msg);
 
 }  // namespace cg

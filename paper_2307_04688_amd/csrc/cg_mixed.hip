@@ -26,9 +26,14 @@
 namespace cg {
 
 // G[i] = V_i transformed (DCT-I) along mode i only.
-__global__ __launch_bounds__(256) void k_taylor_a(const GameConst *__restrict__ gc, const GameStatus *st,
-                                                  const double *Vbuf, double *G)
+__global__ __launch_bounds__(256) void k_taylor_a(const Inst *__restrict__ tab, int bpi)
 {
+    const Inst &I = tab[blockIdx.x / bpi];
+    const int blk = blockIdx.x % bpi;
+    const GameConst *__restrict__ gc = I.gc;
+    const GameStatus *st = I.st;
+    const double *Vbuf = I.V;
+    double *G = I.G;
     __shared__ double Dm[kMaxN * (kMaxN + 1)];
     if (st->converged) return;
     const int N = gc->N, d = gc->d;
@@ -36,7 +41,7 @@ __global__ __launch_bounds__(256) void k_taylor_a(const GameConst *__restrict__ 
     for (int e = threadIdx.x; e < N * N; e += blockDim.x) Dm[(e / N) * LD + e % N] = gc->Dx[(e / N) * kMaxN + e % N];
     __syncthreads();
     const int NN = (int)gc->NN;
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int t = blk * blockDim.x + threadIdx.x;
     if (t >= d * NN) return;
     const int i = t / NN, idx = t % NN;
     int stride = 1;
@@ -51,9 +56,14 @@ __global__ __launch_bounds__(256) void k_taylor_a(const GameConst *__restrict__ 
 // E[i][slot][jm][col]: slot 0 = G_i at (jm, col), slot 1 + s = G_i
 // differentiated at the nodes along mode om_s (the s-th mode other than i).
 // jm enumerates the modes other than i in increasing order; col = k_i.
-__global__ __launch_bounds__(256) void k_taylor_b(const GameConst *__restrict__ gc, const GameStatus *st,
-                                                  const double *__restrict__ G, double *E)
+__global__ __launch_bounds__(256) void k_taylor_b(const Inst *__restrict__ tab, int bpi)
 {
+    const Inst &I = tab[blockIdx.x / bpi];
+    const int blk = blockIdx.x % bpi;
+    const GameConst *__restrict__ gc = I.gc;
+    const GameStatus *st = I.st;
+    const double *__restrict__ G = I.G;
+    double *E = I.E;
     __shared__ double Dm[kMaxN * (kMaxN + 1)];
     if (st->converged) return;
     const int N = gc->N, d = gc->d, NC = gc->NC;
@@ -61,7 +71,7 @@ __global__ __launch_bounds__(256) void k_taylor_b(const GameConst *__restrict__ 
     for (int e = threadIdx.x; e < N * N; e += blockDim.x) Dm[(e / N) * LD + e % N] = gc->Dd[(e / N) * kMaxN + e % N];
     __syncthreads();
     const int NN = (int)gc->NN, NM = NN / N;
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int t = blk * blockDim.x + threadIdx.x;
     if (t >= d * d * NN) return;
     const int col = t % N;
     const int jm = (t / N) % NM;
@@ -98,11 +108,11 @@ __global__ __launch_bounds__(256) void k_taylor_b(const GameConst *__restrict__ 
 
 hipError_t launch_taylor(const GameConst &hc, const StepBuffers &b, hipStream_t s)
 {
-    const long long na = hc.d * hc.NN, nb = (long long)hc.d * hc.d * hc.NN;
-    hipLaunchKernelGGL(k_taylor_a, dim3((unsigned)((na + 255) / 256)), dim3(256), 0, s, b.gc, b.status, b.V, b.G);
+    const int ba = (int)((hc.d * hc.NN + 255) / 256), bb = (int)(((long long)hc.d * hc.d * hc.NN + 255) / 256);
+    hipLaunchKernelGGL(k_taylor_a, dim3((unsigned)(ba * b.count)), dim3(256), 0, s, b.tab, ba);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_taylor_b, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, b.gc, b.status, b.G, b.E);
+    hipLaunchKernelGGL(k_taylor_b, dim3((unsigned)(bb * b.count)), dim3(256), 0, s, b.tab, bb);
     return hipGetLastError();
 }
 
@@ -135,12 +145,17 @@ struct ModeRec {
 };
 
 template <int D, int N4, int NC, int RB>
-__global__ __launch_bounds__(256) void k_contract_corr(const GameConst *__restrict__ gc, const GameStatus *st,
-                                                       const double *__restrict__ Ubuf,
-                                                       const float *__restrict__ Bp32,
-                                                       const double *__restrict__ E, double *__restrict__ Wout,
+__global__ __launch_bounds__(256) void k_contract_corr(const Inst *__restrict__ tab, int bpi,
                                                        int blocks_per_player)
 {
+    const Inst &I = tab[blockIdx.x / bpi];
+    const int blk = blockIdx.x % bpi;
+    const GameConst *__restrict__ gc = I.gc;
+    const GameStatus *st = I.st;
+    const double *__restrict__ Ubuf = I.U;
+    const float *__restrict__ Bp32 = I.Bp32;
+    const double *__restrict__ E = I.E;
+    double *__restrict__ Wout = I.W;
     constexpr int NCB = NC / 16;
     constexpr int ROWS_W = RB * 16;
     constexpr int ROWS_B = 4 * ROWS_W;
@@ -159,8 +174,8 @@ __global__ __launch_bounds__(256) void k_contract_corr(const GameConst *__restri
 
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int r16 = lane & 15, kq = lane >> 4;
-    const int player = blockIdx.x / blocks_per_player;
-    const int tile = blockIdx.x % blocks_per_player;
+    const int player = blk / blocks_per_player;
+    const int tile = blk % blocks_per_player;
     const int row0 = tile * ROWS_B + wave * ROWS_W;
 
     int om[D - 1];
@@ -347,16 +362,26 @@ __global__ __launch_bounds__(256) void k_contract_corr(const GameConst *__restri
         }
 }
 
+template <int D, int N4, int RB>
+static hipError_t launch_corr_dnr(const GameConst &hc, const StepBuffers &b, hipStream_t s)
+{
+    constexpr int NC = N4 <= 16 ? 16 : 32;
+    const int NN = (int)hc.NN;
+    const int bpp = (NN + 4 * RB * 16 - 1) / (4 * RB * 16);
+    const int bpi = bpp * D;
+    hipLaunchKernelGGL((k_contract_corr<D, N4, NC, RB>), dim3((unsigned)(bpi * b.count)), dim3(256), 0, s, b.tab, bpi,
+                       bpp);
+    return hipGetLastError();
+}
+
 template <int D, int N4>
 static hipError_t launch_corr_dn(const GameConst &hc, const StepBuffers &b, hipStream_t s)
 {
-    constexpr int NC = N4 <= 16 ? 16 : 32;
-    constexpr int RB = 2;
-    const int NN = (int)hc.NN;
-    const int bpp = (NN + 4 * RB * 16 - 1) / (4 * RB * 16);
-    hipLaunchKernelGGL((k_contract_corr<D, N4, NC, RB>), dim3(bpp * D), dim3(256), 0, s, b.gc, b.status, b.U,
-                       b.Bp32, b.E, b.W, bpp);
-    return hipGetLastError();
+    switch (b.rb) {
+        case 1: return launch_corr_dnr<D, N4, 1>(hc, b, s);
+        case 4: return launch_corr_dnr<D, N4, 4>(hc, b, s);
+        default: return launch_corr_dnr<D, N4, 2>(hc, b, s);
+    }
 }
 
 template <int D>

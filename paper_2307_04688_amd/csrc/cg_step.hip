@@ -33,11 +33,15 @@ namespace cg {
 // slab s+1 into registers while its waves run the MFMAs of slab s.  The
 // result rows go to W[i][j][0..NC) (L2/MALL-resident) for the line kernel.
 template <int D, int N4, int NC, int RB>
-__global__ __launch_bounds__(256) void k_contract_f64(const GameConst *__restrict__ gc, const GameStatus *st,
-                                                      const double *__restrict__ Ubuf,
-                                                      const double *__restrict__ Bp, double *__restrict__ Wout,
-                                                      int blocks_per_player)
+__global__ __launch_bounds__(256) void k_contract_f64(const Inst *__restrict__ tab, int bpi, int blocks_per_player)
 {
+    const Inst &I = tab[blockIdx.x / bpi];
+    const int blk = blockIdx.x % bpi;
+    const GameConst *__restrict__ gc = I.gc;
+    const GameStatus *st = I.st;
+    const double *__restrict__ Ubuf = I.U;
+    const double *__restrict__ Bp = I.Bp;
+    double *__restrict__ Wout = I.W;
     constexpr int NCB = NC / 16;
     constexpr int ROWS_W = RB * 16;
     constexpr int ROWS_B = 4 * ROWS_W;
@@ -55,8 +59,8 @@ __global__ __launch_bounds__(256) void k_contract_f64(const GameConst *__restric
 
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int r16 = lane & 15, kq = lane >> 4;
-    const int player = blockIdx.x / blocks_per_player;
-    const int tile = blockIdx.x % blocks_per_player;
+    const int player = blk / blocks_per_player;
+    const int tile = blk % blocks_per_player;
     const int row0 = tile * ROWS_B + wave * ROWS_W;
 
     int om[D - 1];  // other modes in increasing order
@@ -221,10 +225,14 @@ __device__ void finish_step(const GameConst *__restrict__ gc, GameStatus *st, in
 // each samples half of the control nodes, and the partial fits are summed
 // through LDS.
 template <int D, int N4, int NC, bool COMPOSE>
-__global__ __launch_bounds__(256) void k_line_f64(const GameConst *__restrict__ gc, GameStatus *st, double *Vbuf,
-                                                  double *Ubuf, const double *__restrict__ Win,
-                                                  int blocks_per_player)
+__global__ __launch_bounds__(256) void k_line_f64(const Inst *__restrict__ tab, int bpi, int blocks_per_player)
 {
+    const Inst &I = tab[blockIdx.x / bpi];
+    const int blk = blockIdx.x % bpi;
+    const GameConst *__restrict__ gc = I.gc;
+    GameStatus *st = I.st;
+    double *Vbuf = I.V, *Ubuf = I.U;
+    const double *__restrict__ Win = I.W;
     constexpr int TPR = COMPOSE ? 1 : 2;
     constexpr int ROWS_B = 256 / TPR;
     __shared__ double Qx[COMPOSE ? 1 : N4 * ROWS_B];
@@ -239,8 +247,8 @@ __global__ __launch_bounds__(256) void k_line_f64(const GameConst *__restrict__ 
     double *Unew = Ubuf + (long long)(1 - cur) * D * NN;
 
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int player = blockIdx.x / blocks_per_player;
-    const int tile = blockIdx.x % blocks_per_player;
+    const int player = blk / blocks_per_player;
+    const int tile = blk % blocks_per_player;
     const int row = tid % ROWS_B;
     const int part = tid / ROWS_B;
     const int j = tile * ROWS_B + row;
@@ -298,20 +306,30 @@ __global__ __launch_bounds__(256) void k_line_f64(const GameConst *__restrict__ 
         }
         atomicMax(&st->res_bits[cur], m);
         __threadfence();
-        if (atomicAdd(&st->blocks_done, 1u) == gridDim.x - 1) {
+        if (atomicAdd(&st->blocks_done, 1u) == (unsigned)bpi - 1u) {
             __threadfence();
             finish_step(gc, st, cur);
         }
     }
 }
 
+template <int D, int N4, int RB>
+static hipError_t launch_contract_dnr(const GameConst &hc, const StepBuffers &b, hipStream_t s)
+{
+    constexpr int NC = N4 <= 16 ? 16 : 32;
+    const int NN = (int)hc.NN;
+    const int bpp = (NN + 4 * RB * 16 - 1) / (4 * RB * 16);
+    const int bpi = bpp * D;
+    hipLaunchKernelGGL((k_contract_f64<D, N4, NC, RB>), dim3((unsigned)(bpi * b.count)), dim3(256), 0, s, b.tab, bpi,
+                       bpp);
+    return hipGetLastError();
+}
+
 template <int D, int N4>
 static hipError_t launch_step_dn(const GameConst &hc, const StepBuffers &b, hipStream_t s)
 {
     constexpr int NC = N4 <= 16 ? 16 : 32;
-    constexpr int RB = 2;  // 32 rows per wave
     const int NN = (int)hc.NN;
-    const int bpp = (NN + 4 * RB * 16 - 1) / (4 * RB * 16);
     hipError_t e;
     if (b.precision == CG_FP32_CORR) {
         e = launch_taylor(hc, b, s);
@@ -324,9 +342,11 @@ static hipError_t launch_step_dn(const GameConst &hc, const StepBuffers &b, hipS
     if (b.precision == CG_FP32_CORR) {
         e = launch_contract_corr(hc, b, s);
     } else {
-        hipLaunchKernelGGL((k_contract_f64<D, N4, NC, RB>), dim3(bpp * D), dim3(256), 0, s, b.gc, b.status, b.U,
-                           b.Bp, b.W, bpp);
-        e = hipGetLastError();
+        switch (b.rb) {
+            case 1: e = launch_contract_dnr<D, N4, 1>(hc, b, s); break;
+            case 4: e = launch_contract_dnr<D, N4, 4>(hc, b, s); break;
+            default: e = launch_contract_dnr<D, N4, 2>(hc, b, s); break;
+        }
     }
     if (e != hipSuccess) return e;
     if (b.ev_end) {
@@ -335,12 +355,14 @@ static hipError_t launch_step_dn(const GameConst &hc, const StepBuffers &b, hipS
     }
     if (hc.Nu >= hc.N) {  // the fit in u is exact: compose the series directly
         const int lpp = (NN + 255) / 256;
-        hipLaunchKernelGGL((k_line_f64<D, N4, NC, true>), dim3(lpp * D), dim3(256), 0, s, b.gc, b.status, b.V, b.U,
-                           b.W, lpp);
+        const int bpi = lpp * D;
+        hipLaunchKernelGGL((k_line_f64<D, N4, NC, true>), dim3((unsigned)(bpi * b.count)), dim3(256), 0, s, b.tab,
+                           bpi, lpp);
     } else {
         const int lpp = (NN + 127) / 128;
-        hipLaunchKernelGGL((k_line_f64<D, N4, NC, false>), dim3(lpp * D), dim3(256), 0, s, b.gc, b.status, b.V, b.U,
-                           b.W, lpp);
+        const int bpi = lpp * D;
+        hipLaunchKernelGGL((k_line_f64<D, N4, NC, false>), dim3((unsigned)(bpi * b.count)), dim3(256), 0, s, b.tab,
+                           bpi, lpp);
     }
     return hipGetLastError();
 }

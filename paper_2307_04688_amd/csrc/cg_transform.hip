@@ -94,9 +94,15 @@ __device__ __forceinline__ long long packed_index(const GameConst *__restrict__ 
     return ((long long)i * gc->K + (long long)kout * gc->N4 + kl) * gc->NC + col;
 }
 
-__global__ __launch_bounds__(256) void k_tf_fast(const GameConst *__restrict__ gc, const GameStatus *st,
-                                                 const double *Vbuf, double *out, double *Bp, float *Bp32)
+__global__ __launch_bounds__(256) void k_tf_fast(const Inst *__restrict__ tab, int bpi, int mixed)
 {
+    const Inst &I = tab[blockIdx.x / bpi];
+    const int blk = blockIdx.x % bpi;
+    const GameConst *__restrict__ gc = I.gc;
+    const GameStatus *st = I.st;
+    const double *Vbuf = I.V;
+    double *out = I.tmp, *Bp = I.Bp;
+    float *Bp32 = mixed ? I.Bp32 : nullptr;
     constexpr int LD = kMaxN + 1;  // odd stride: column reads hit distinct banks
     __shared__ double Dm[kMaxN * LD];
     __shared__ double X[kMaxN * LD];
@@ -105,7 +111,7 @@ __global__ __launch_bounds__(256) void k_tf_fast(const GameConst *__restrict__ g
     const int N = gc->N, d = gc->d, NN2 = N * N;
     const long long NN = gc->NN;
     const int nslice = (int)(NN / NN2);
-    const int i = blockIdx.x / nslice, sl = blockIdx.x % nslice;
+    const int i = blk / nslice, sl = blk % nslice;
     const double *src = Vbuf + (long long)st->cur * d * NN + (long long)i * NN + (long long)sl * NN2;
     for (int e = threadIdx.x; e < NN2; e += blockDim.x) {
         Dm[(e / N) * LD + e % N] = gc->Dx[(e / N) * kMaxN + e % N];
@@ -165,16 +171,22 @@ __global__ __launch_bounds__(256) void k_tf_fast(const GameConst *__restrict__ g
 
 // Tile of the outer modes: X[f][q], f over the N^(d-2) outer positions,
 // q over Q consecutive inner positions (the two fast modes flattened).
-__global__ __launch_bounds__(256) void k_tf_outer(const GameConst *__restrict__ gc, const GameStatus *st,
-                                                  const double *__restrict__ in, double *Bp, float *Bp32, int Q)
+__global__ __launch_bounds__(256) void k_tf_outer(const Inst *__restrict__ tab, int bpi, int mixed, int Q)
 {
+    const Inst &I = tab[blockIdx.x / bpi];
+    const int blk = blockIdx.x % bpi;
+    const GameConst *__restrict__ gc = I.gc;
+    const GameStatus *st = I.st;
+    const double *__restrict__ in = I.tmp;
+    double *Bp = I.Bp;
+    float *Bp32 = mixed ? I.Bp32 : nullptr;
     extern __shared__ double sh[];
     if (st->converged) return;
     const int N = gc->N, d = gc->d, NN2 = N * N;
     const long long NN = gc->NN;
     const int F = (int)(NN / NN2);          // N^(d-2) outer positions
     const int nq = (NN2 + Q - 1) / Q;       // tiles per player
-    const int i = blockIdx.x / nq, q0 = (blockIdx.x % nq) * Q;
+    const int i = blk / nq, q0 = (blk % nq) * Q;
     constexpr int LD = kMaxN + 1;
     double *Dm = sh;                        // N x N, row stride LD
     double *X = sh + kMaxN * LD;            // F x Q
@@ -219,10 +231,10 @@ __global__ __launch_bounds__(256) void k_tf_outer(const GameConst *__restrict__ 
 hipError_t launch_transform_game(const GameConst &hc, const StepBuffers &b, hipStream_t s)
 {
     const int N = hc.N, d = hc.d;
+    const int mixed = b.precision == CG_FP32_CORR;  // packed operand in binary32
     const long long nslice = hc.NN / (N * N);
-    float *Bp32 = b.precision == CG_FP32_CORR ? b.Bp32 : nullptr;  // packed operand in binary32
-    hipLaunchKernelGGL(k_tf_fast, dim3((unsigned)(nslice * d)), dim3(256), 0, s, b.gc, b.status, b.V, b.tmp, b.Bp,
-                       Bp32);
+    const int bpi1 = (int)(nslice * d);
+    hipLaunchKernelGGL(k_tf_fast, dim3((unsigned)(bpi1 * b.count)), dim3(256), 0, s, b.tab, bpi1, mixed);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || d == 2) return e;
     // Q inner positions per tile, so that the dynamic LDS (D plus one or two
@@ -233,8 +245,8 @@ hipError_t launch_transform_game(const GameConst &hc, const StepBuffers &b, hipS
     Q = Q > 16 ? 16 : (Q < 1 ? 1 : Q);
     const size_t shmem = sizeof(double) * ((size_t)kMaxN * (kMaxN + 1) + (size_t)tiles * F * Q);
     const int nq = (N * N + Q - 1) / Q;
-    hipLaunchKernelGGL(k_tf_outer, dim3((unsigned)(nq * d)), dim3(256), shmem, s, b.gc, b.status, b.tmp, b.Bp, Bp32,
-                       Q);
+    const int bpi2 = nq * d;
+    hipLaunchKernelGGL(k_tf_outer, dim3((unsigned)(bpi2 * b.count)), dim3(256), shmem, s, b.tab, bpi2, mixed, Q);
     return hipGetLastError();
 }
 

@@ -1,0 +1,126 @@
+"""Batched value iteration (cg_batch_*): one graph-replayed iteration over a
+ragged set of games must give each game exactly what its own solve gives."""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def cg():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2307_04688_amd import chebgame
+    chebgame.lib()
+    return chebgame
+
+
+def ragged(count, seed=11, h=1e-2):
+    games = []
+    for i in range(count):
+        u = W.uniform(seed, 7000 + i, np.arange(2, dtype=np.uint64))
+        d = 2 + int(u[0] * 2)
+        N = (6, 9, 12, 16)[int(u[1] * 4)]
+        games.append(W.make_game(d, N, seed=seed, instance=i, h=h))
+    return games
+
+
+@pytest.mark.parametrize("prec", ["FP64", "FP32_CORR"])
+def test_batch_equals_individual_solves(cg, prec):
+    p = getattr(cg, prec)
+    games = ragged(10)
+    say(f"batch {prec}: {[(g.d, g.N) for g in games]}")
+    handles = [cg.ChebGame(g, p) for g in games]
+    B = cg.ChebBatch(handles)
+    rc, steps, res = B.solve(25)
+    assert rc == cg.OK and np.all(steps == 25)
+    for g, h in zip(games, handles):
+        single = cg.ChebGame(g, p)
+        _, n1, r1 = single.solve(25)
+        V1, U1, _ = single.get_state()
+        Vb, Ub, _ = h.get_state()
+        assert n1 == 25
+        assert torch.equal(V1, Vb) and torch.equal(U1, Ub), (g.d, g.N)
+    assert np.all(np.isfinite(res)) and np.all(res > 0)
+
+
+def test_batch_against_oracle(cg, orc):
+    games = ragged(6, seed=12)
+    handles = [cg.ChebGame(g, cg.FP64) for g in games]
+    B = cg.ChebBatch(handles)
+    B.solve(15)
+    for g, h in zip(games, handles):
+        Vo, Uo, _ = orc.solve(g, 15)
+        V, U, _ = h.get_state()
+        e = np.max(np.abs(V.cpu().numpy() - Vo)) / np.max(np.abs(Vo))
+        assert e <= 1e-12, (g.d, g.N, e)
+        assert np.max(np.abs(U.cpu().numpy() - Uo)) <= 1e-10 * g.u_max
+
+
+def test_batch_convergence_per_instance(cg):
+    """Each game stops at its own first residual below tol, exactly where its
+    own solve stops; with a long step (h = 0.2) one of these games keeps
+    cycling (the oracle's residual for it stays near 2e-3 too), so the batch
+    reports not-converged while the others have stopped."""
+    games = ragged(8, seed=13, h=0.2)
+    tol = 1e-6
+    handles = [cg.ChebGame(g, cg.FP64) for g in games]
+    B = cg.ChebBatch(handles)
+    rc, steps, res = B.solve(1500, tol)
+    say(f"  rc {rc} steps {steps.tolist()}")
+    single_rc = []
+    for g, n, r in zip(games, steps, res):
+        single = cg.ChebGame(g, cg.FP64)
+        rc1, n1, r1 = single.solve(1500, tol)
+        single_rc.append(rc1)
+        assert n1 == n and r1 == r, (g.d, g.N, n, n1)
+        assert (rc1 == cg.OK) == (r < tol) and (n < 1500 or r >= tol)
+    assert rc == (cg.OK if all(c == cg.OK for c in single_rc) else cg.ENOTCONVERGED)
+    assert sum(c == cg.OK for c in single_rc) >= 6
+    # a second solve continues every game from its state
+    rc, steps2, res2 = B.solve(4)
+    assert rc == cg.OK and np.all(steps2 == 4)
+
+
+def test_batch_not_converged_status(cg):
+    games = ragged(3, seed=14)
+    B = cg.ChebBatch([cg.ChebGame(g, cg.FP64) for g in games])
+    rc, steps, res = B.solve(3, 1e-14)
+    assert rc == cg.ENOTCONVERGED and np.all(steps == 3)
+
+
+def test_batch_autotune_and_reset(cg):
+    games = ragged(6, seed=15)
+    handles = [cg.ChebGame(g, cg.FP32_CORR) for g in games]
+    B = cg.ChebBatch(handles)
+    rb = B.autotune(2)
+    assert len(rb) == B.groups().__len__() and all(r in (1, 2, 4) for r in rb)
+    rc, steps, _ = B.solve(12)
+    assert np.all(steps == 12)
+    for g, h in zip(games, handles):
+        single = cg.ChebGame(g, cg.FP32_CORR)
+        single.solve(12)
+        V1 = single.get_state()[0]
+        Vb = h.get_state()[0]
+        assert torch.max(torch.abs(V1 - Vb)) <= 1e-12 * torch.max(torch.abs(V1)), (g.d, g.N)
+
+
+def test_batch_errors(cg):
+    g = W.make_game(2, 8, seed=1)
+    h = cg.ChebGame(g, cg.FP64)
+    with pytest.raises(cg.ChebGameError) as e:
+        cg.ChebBatch([h, h])
+    assert e.value.code == cg.EINVAL
+    with pytest.raises(cg.ChebGameError) as e:
+        cg.ChebBatch([])
+    assert e.value.code == cg.EINVAL
