@@ -194,3 +194,28 @@ def batch_games(count: int = 256, seed: int = 4):
         N = (12, 16, 24, 32)[int(u[1] * 4)]
         out.append(make_game(d, N, seed=seed, instance=inst))
     return out
+
+
+# ---- warm-start network inputs ----
+
+MLP_LAYERS = ((9, 256), (256, 256), (256, 256), (256, 3))
+
+
+def mlp_init(seed: int = 7) -> np.ndarray:
+    """Flat FP32 initial parameters (W1, b1, ..., W4, b4; W stored
+    [fan_in][fan_out]): normal weights with variance 2/fan_in (1/fan_in for
+    the linear output layer), zero biases."""
+    out = []
+    for l, (a, b) in enumerate(MLP_LAYERS):
+        std = np.sqrt((1.0 if l == len(MLP_LAYERS) - 1 else 2.0) / a)
+        out.append(std * normal(seed, 9000 + l, a * b))
+        out.append(np.zeros(b))
+    return np.concatenate(out).astype(np.float32)
+
+
+def theta_features(game) -> np.ndarray:
+    """The six game parameters (A, beta, phi, c, kappa, rho) as theta/nominal - 1,
+    in [-0.5, 0.5) for the seeded draws."""
+    th = np.asarray(game.theta, dtype=np.float64)
+    nom = np.array([NOMINAL[k] for k in THETA_ORDER])
+    return (th / nom - 1.0).astype(np.float32)
