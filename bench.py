@@ -143,6 +143,107 @@ def run_batch(cg, W, torch, steps: int, warmup: int, count: int = 256, time_step
             "instances_rel_V_above_1e-8": int(np.sum(np.array(errs) > 1e-8))}
 
 
+def run_warm(cg, W, torch, n_train: int = 128, n_test: int = 16, N: int = 24, train_tol: float = 1e-7,
+             tol: float = 1e-8, max_steps: int = 40000):
+    """Learned warm start on d=3 games (seed 5): the network is trained on
+    `n_train` games solved by the method (batched, FP32 MFMA + FP64
+    correction, to residual `train_tol`), then `n_test` held-out games are
+    solved to residual `tol` (a) plainly: FP64, one at a time, from zero, and
+    (b) in the chosen form: FP32 MFMA + FP64 correction, batched, from the
+    network's start, with the plain zero start as fallback for any game that
+    does not converge."""
+    import numpy as np
+    log = lambda *a: print("bench:", *a, file=sys.stderr, flush=True)
+    train = [W.make_game(3, N, seed=5, instance=i) for i in range(n_train)]
+    test = [W.make_game(3, N, seed=5, instance=100000 + i) for i in range(n_test)]
+    t0 = time.perf_counter()
+    hs = [cg.ChebGame(g, cg.FP32_CORR) for g in train]
+    B = cg.ChebBatch(hs)
+    for chunk in range(max_steps // 2000):
+        _, _, res = B.solve(2000, train_tol)
+        done = ~np.isfinite(res) | (res < train_tol)
+        log(f"training data: {2000 * (chunk + 1)} iterations, {int(done.sum())}/{n_train} games done")
+        if done.all():
+            break
+    t_data = time.perf_counter() - t0
+    good = np.isfinite(res) & (res < train_tol)
+    log(f"training data: {int(good.sum())}/{n_train} games converged in {t_data:.1f} s")
+    Xs, Ts = [], []
+    for g, h, ok in zip(train, hs, good):
+        if ok:
+            X, T = cg.mlp_features(h, W.theta_features(g), t_scale=g.rho)
+            Xs.append(X)
+            Ts.append(T)
+    for h in hs:
+        h.destroy()
+    X, T = torch.cat(Xs), torch.cat(Ts)
+    net = cg.MLP(W.mlp_init(seed=1), batch=8192)
+    t0 = time.perf_counter()
+    l0 = net.train(X, T, steps=4000, lr=1e-3, seed=2)
+    net.train(X, T, steps=3000, lr=3e-4, seed=3)
+    l1 = net.train(X, T, steps=3000, lr=1e-4, seed=4)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    log(f"trained 10000 Adam steps in {t_train:.1f} s")
+    # (a) plain: FP64, one at a time, from zero
+    plain_it, plain_ok, Vref = [], [], []
+    t0 = time.perf_counter()
+    for g in test:
+        h = cg.ChebGame(g, cg.FP64)
+        try:
+            rc, n, r = h.solve(max_steps, tol)
+            plain_ok.append(rc == cg.OK)
+        except cg.ChebGameError:
+            plain_ok.append(False)
+            n = max_steps
+        plain_it.append(n)
+        log(f"plain solve {len(plain_it)}/{n_test}: {n} iterations")
+        Vref.append(h.get_state()[0] if plain_ok[-1] else None)
+        h.destroy()
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    # (b) chosen form: warm start, mixed precision, batched; fallback to zero
+    t0 = time.perf_counter()
+    hw = [cg.ChebGame(g, cg.FP32_CORR) for g in test]
+    bad = [net.warm_start(h, W.theta_features(g), 1.0 / g.rho) for g, h in zip(test, hw)]
+    _, wsteps, wres = cg.ChebBatch(hw).solve(max_steps, tol)
+    fell = []
+    for k, (g, h) in enumerate(zip(test, hw)):
+        if not (np.isfinite(wres[k]) and wres[k] < tol):
+            h.reset()
+            try:
+                _, n, r = h.solve(max_steps, tol)
+            except cg.ChebGameError:
+                n, r = max_steps, float("nan")
+            wsteps[k] += n
+            wres[k] = r
+            fell.append(k)
+    torch.cuda.synchronize()
+    t_warm = time.perf_counter() - t0
+    errs = []
+    for k, h in enumerate(hw):
+        if Vref[k] is not None and np.isfinite(wres[k]) and wres[k] < tol:
+            V = h.get_state()[0]
+            errs.append((torch.max(torch.abs(V - Vref[k])) / torch.max(torch.abs(Vref[k]))).item())
+    both = [k for k in range(n_test) if plain_ok[k] and np.isfinite(wres[k]) and wres[k] < tol]
+    pi = np.array([plain_it[k] for k in both])
+    wi = np.array([wsteps[k] for k in both])
+    return {"workload": f"learned warm start, d=3 N={N} (seed 5): {n_train} training games, {n_test} held-out",
+            "train_games_converged": int(good.sum()), "train_samples": int(X.shape[0]),
+            "data_generation_s": t_data, "training_s": t_train,
+            "train_loss_first": float(l0[:10].mean().item()), "train_loss_last": float(l1[-100:].mean().item()),
+            "tol": tol, "held_out_converged_both": len(both),
+            "plain_fp64_zero_iterations_mean": float(pi.mean()) if len(pi) else None,
+            "warm_iterations_mean": float(wi.mean()) if len(wi) else None,
+            "plain_fp64_zero_iterations_median": float(np.median(pi)) if len(pi) else None,
+            "warm_iterations_median": float(np.median(wi)) if len(wi) else None,
+            "iteration_ratio": float(wi.mean() / pi.mean()) if len(pi) else None,
+            "plain_fp64_one_at_a_time_solves_per_s": n_test / t_plain,
+            "chosen_mixed_batched_warm_solves_per_s": n_test / t_warm,
+            "speedup": t_plain / t_warm, "fallbacks": len(fell) + int(sum(bad)),
+            "max_rel_V_vs_plain": max(errs) if errs else None}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -150,7 +251,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32corr"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="c2", choices=["c2", "batch"])
+    ap.add_argument("--workload", default="c2", choices=["c2", "batch", "warm"])
     ap.add_argument("--cpu-steps", type=int, default=6, help="oracle iterations timed for the CPU baseline")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for scaling rocprof byte counters)")
@@ -169,6 +270,9 @@ def main():
     if args.workload == "batch":
         print("bench: ragged batch of 256 games", file=sys.stderr, flush=True)
         print(json.dumps(run_batch(cg, W, torch, args.steps, args.warmup)), flush=True)
+        return
+    if args.workload == "warm":
+        print(json.dumps(run_warm(cg, W, torch)), flush=True)
         return
     g = W.config_game("C2")
     prec = cg.FP64 if args.precision == "fp64" else cg.FP32_CORR

@@ -195,6 +195,74 @@ int cg_batch_solve(cg_batch *batch, int32_t max_steps, double tol, int32_t *step
 int cg_batch_groups(cg_batch *batch, int32_t *rb);
 int cg_batch_destroy(cg_batch *batch);
 
+/* Learned warm start (an addition to the method: Section 2.2 leaves the
+ * starting iterate V^[0] free; the network only chooses it, and the iteration
+ * that follows is the plain method, which also judges the result).
+ *
+ * Network: 9 inputs (the six game parameters (A, beta, phi, c, kappa, rho) as
+ * theta/nominal - 1, then the three normalised state coordinates x in
+ * [-1,1]^3 of a node) -> 256 -> 256 -> 256 GELU units (gelu(z) = z Phi(z)) ->
+ * 3 outputs (the players' values at the node, scaled).  binary32 throughout.
+ * Parameters: one device array of cg_mlp_param_count() floats, per layer W
+ * ([fan_in][fan_out], row-major) then b, layers in order.  Loss: mean over
+ * samples and outputs of (y - t)^2.  Samples X are [n][9], outputs and
+ * targets [n][3], device, binary32.
+ *
+ * Workspaces (device, 256-byte aligned, >= cg_mlp_workspace_bytes(batch)):
+ * scratch of the calls below for minibatches of up to 'batch' rows (1 ..
+ * 65536); 0 = batch out of range.  All calls queue work on 'stream' (the
+ * game's stream for the game-level calls) and return at once unless stated.
+ *
+ * cg_mlp_forward: Y = net(X) for n rows, 'batch' rows at a time.
+ * cg_mlp_grad: loss (device float, nullable) and gradient (device, same
+ *   layout as the parameters) of one minibatch of n <= 65536 rows; ws must
+ *   fit n rows.  Sums are taken in a fixed order: reruns are bitwise equal.
+ * cg_mlp_adam: one Adam step t >= 1 (Kingma and Ba, bias-corrected) of the
+ *   parameters with moment arrays m, v (device, parameter layout).
+ * cg_mlp_train: 'steps' Adam steps t0+1 .. t0+steps at learning rate lr
+ *   (beta1 0.9, beta2 0.999, eps 1e-8), each on 'batch' rows drawn with
+ *   replacement from the n_samples rows of (X, T) by SplitMix64 of (seed,
+ *   step, row); losses (device, 'steps' floats, nullable) gets each step's
+ *   minibatch loss.
+ * theta (game-level calls): host array of the six normalised parameters.
+ * cg_mlp_features: writes the N^3 feature rows of a d = 3 game's nodes into X
+ *   (node order of V) and, if T is not NULL, t_scale * V_i of the game's
+ *   current state into T: training pairs from a solved game.
+ * cg_warm_start: V^[0] = out_scale * net(features) at every node and u^[0]_i
+ *   = clip(A_i + delta_h beta_i dV^[0]_i/dp_i, 0, U_M), the maximiser of
+ *   Step 3's objective with V^[0] expanded to first order at the node.  If
+ *   any value of V^[0] is non-finite the game is set to the zero start
+ *   (V = 0, u = A) instead and *nonfinite (host, nullable) is 1.
+ *   Synchronises.
+ * cg_solve_warm: cg_solve to tol from the warm start, with the plain method as
+ *   fallback: one iteration from the zero start gives the bar r0; after the
+ *   warm start, probe_steps iterations must leave a finite residual <= r0, or
+ *   the game restarts from zero and is solved plainly (*fell_back = 1).
+ *   *steps_done counts every iteration spent (the bar, the probe, the rest).
+ *   Synchronises; returns as cg_solve.
+ * Calls other than cg_mlp_param_count and cg_mlp_workspace_bytes return
+ * CG_EUNSUPPORTED for games with d != 3. */
+#define CG_MLP_IN 9
+#define CG_MLP_HIDDEN 256
+#define CG_MLP_OUT 3
+int64_t cg_mlp_param_count(void);
+size_t cg_mlp_workspace_bytes(int32_t batch);
+int cg_mlp_forward(const float *params, const float *X, int64_t n, float *Y, int32_t batch, void *ws,
+                   size_t ws_bytes, void *stream);
+int cg_mlp_grad(const float *params, const float *X, const float *T, int32_t n, float *grad, float *loss, void *ws,
+                size_t ws_bytes, void *stream);
+int cg_mlp_adam(float *params, const float *grad, float *m, float *v, int32_t t, float lr, float beta1, float beta2,
+                float eps, void *stream);
+int cg_mlp_train(float *params, float *m, float *v, const float *X, const float *T, int64_t n_samples, int32_t batch,
+                 int32_t steps, int32_t t0, float lr, uint64_t seed, float *losses, void *ws, size_t ws_bytes,
+                 void *stream);
+int cg_mlp_features(cg_game *game, const float *theta, double t_scale, float *X, float *T);
+int cg_warm_start(cg_game *game, const float *params, const float *theta, double out_scale, void *ws,
+                  size_t ws_bytes, int32_t batch, int32_t *nonfinite);
+int cg_solve_warm(cg_game *game, const float *params, const float *theta, double out_scale, int32_t max_steps,
+                  double tol, int32_t probe_steps, void *ws, size_t ws_bytes, int32_t batch, int32_t *steps_done,
+                  double *residual, int32_t *fell_back);
+
 /* Timing of the contraction kernel (the fused step kernel that carries the
  * mode-n contractions).  With enable != 0, every later step records a pair of
  * HIP events on the game's stream around that kernel's launch.  If kernel_ms

@@ -76,6 +76,19 @@ def lib() -> C.CDLL:
     L.cg_batch_solve.argtypes = [vp, C.c_int32, C.c_double, ip, dp]
     L.cg_batch_groups.argtypes = [vp, ip]
     L.cg_batch_destroy.argtypes = [vp]
+    fp = C.POINTER(C.c_float)
+    L.cg_mlp_param_count.restype = C.c_int64
+    L.cg_mlp_workspace_bytes.restype = C.c_size_t
+    L.cg_mlp_workspace_bytes.argtypes = [C.c_int32]
+    L.cg_mlp_forward.argtypes = [vp, vp, C.c_int64, vp, C.c_int32, vp, C.c_size_t, vp]
+    L.cg_mlp_grad.argtypes = [vp, vp, vp, C.c_int32, vp, vp, vp, C.c_size_t, vp]
+    L.cg_mlp_adam.argtypes = [vp, vp, vp, vp, C.c_int32, C.c_float, C.c_float, C.c_float, C.c_float, vp]
+    L.cg_mlp_train.argtypes = [vp, vp, vp, vp, vp, C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.c_float,
+                               C.c_uint64, vp, vp, C.c_size_t, vp]
+    L.cg_mlp_features.argtypes = [vp, fp, C.c_double, vp, vp]
+    L.cg_warm_start.argtypes = [vp, vp, fp, C.c_double, vp, C.c_size_t, C.c_int32, ip]
+    L.cg_solve_warm.argtypes = [vp, vp, fp, C.c_double, C.c_int32, C.c_double, C.c_int32, vp, C.c_size_t,
+                                C.c_int32, ip, dp, ip]
     _lib = L
     return L
 
@@ -253,6 +266,115 @@ class ChebBatch:
             self.destroy()
         except Exception:
             pass
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _theta(theta):
+    a = np.ascontiguousarray(np.asarray(theta, dtype=np.float32).ravel())
+    if a.size != 6:
+        raise ChebGameError(EINVAL, "theta must hold six values")
+    return a, a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+class MLP:
+    """The warm-start network: binary32 parameters, Adam moments and a
+    workspace for minibatches of up to `batch` rows, all device tensors."""
+
+    def __init__(self, params=None, batch: int = 4096, stream=None):
+        import torch
+        L = lib()
+        self.P = int(L.cg_mlp_param_count())
+        if params is None:
+            params = np.zeros(self.P, dtype=np.float32)
+        p = torch.as_tensor(np.asarray(params, dtype=np.float32) if not isinstance(params, torch.Tensor) else params)
+        self.params = p.to(device="cuda", dtype=torch.float32).contiguous().clone()
+        if self.params.numel() != self.P:
+            raise ChebGameError(EINVAL, f"expected {self.P} parameters")
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.t = 0
+        self.batch = int(batch)
+        self.stream = stream
+        self.ws = self._ws(self.batch)
+
+    def _ws(self, n):
+        import torch
+        nb = int(lib().cg_mlp_workspace_bytes(n))
+        if nb == 0:
+            raise ChebGameError(EINVAL, "batch out of range")
+        return torch.empty(nb, dtype=torch.uint8, device="cuda")
+
+    def forward(self, X):
+        import torch
+        X = X.to(device="cuda", dtype=torch.float32).contiguous().reshape(-1, 9)
+        Y = torch.empty((X.shape[0], 3), dtype=torch.float32, device="cuda")
+        _check(lib().cg_mlp_forward(_ptr(self.params), _ptr(X), X.shape[0], _ptr(Y), self.batch, _ptr(self.ws),
+                                    self.ws.numel(), C.c_void_p(_stream(self.stream))))
+        return Y
+
+    def grad(self, X, T):
+        """(loss, gradient) of one minibatch, both device tensors."""
+        import torch
+        X = X.to(device="cuda", dtype=torch.float32).contiguous().reshape(-1, 9)
+        T = T.to(device="cuda", dtype=torch.float32).contiguous().reshape(-1, 3)
+        n = X.shape[0]
+        ws = self.ws if n <= self.batch else self._ws(n)
+        g = torch.empty_like(self.params)
+        loss = torch.empty(1, dtype=torch.float32, device="cuda")
+        _check(lib().cg_mlp_grad(_ptr(self.params), _ptr(X), _ptr(T), n, _ptr(g), _ptr(loss), _ptr(ws), ws.numel(),
+                                 C.c_void_p(_stream(self.stream))))
+        self._keep = ws
+        return loss, g
+
+    def adam(self, grad, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):
+        self.t += 1
+        _check(lib().cg_mlp_adam(_ptr(self.params), _ptr(grad), _ptr(self.m), _ptr(self.v), self.t, lr, beta1, beta2,
+                                 eps, C.c_void_p(_stream(self.stream))))
+
+    def train(self, X, T, steps: int, lr: float = 1e-3, seed: int = 1):
+        """`steps` Adam steps on minibatches of `batch` rows drawn from (X, T); per-step losses."""
+        import torch
+        X = X.to(device="cuda", dtype=torch.float32).contiguous().reshape(-1, 9)
+        T = T.to(device="cuda", dtype=torch.float32).contiguous().reshape(-1, 3)
+        losses = torch.empty(max(steps, 1), dtype=torch.float32, device="cuda")
+        _check(lib().cg_mlp_train(_ptr(self.params), _ptr(self.m), _ptr(self.v), _ptr(X), _ptr(T), X.shape[0],
+                                  self.batch, steps, self.t, lr, seed, _ptr(losses), _ptr(self.ws), self.ws.numel(),
+                                  C.c_void_p(_stream(self.stream))))
+        self.t += steps
+        return losses[:steps]
+
+    def warm_start(self, g: "ChebGame", theta, out_scale: float) -> int:
+        """Sets g's state from the network; returns 1 if it fell back to the zero start."""
+        _, tp = _theta(theta)
+        bad = C.c_int32()
+        _check(lib().cg_warm_start(g.handle, _ptr(self.params), tp, float(out_scale), _ptr(self.ws), self.ws.numel(),
+                                   self.batch, C.byref(bad)))
+        return bad.value
+
+    def solve_warm(self, g: "ChebGame", theta, out_scale: float, max_steps: int, tol: float, probe_steps: int = 16):
+        """(status, iterations spent, last residual, fell back)."""
+        _, tp = _theta(theta)
+        n = C.c_int32()
+        r = C.c_double()
+        fb = C.c_int32()
+        rc = _check(lib().cg_solve_warm(g.handle, _ptr(self.params), tp, float(out_scale), max_steps, float(tol),
+                                        probe_steps, _ptr(self.ws), self.ws.numel(), self.batch, C.byref(n),
+                                        C.byref(r), C.byref(fb)))
+        return rc, n.value, r.value, fb.value
+
+
+def mlp_features(g: "ChebGame", theta, t_scale: float = 0.0, with_targets: bool = True):
+    """Feature rows [N^3][9] of g's nodes and targets t_scale * V ([N^3][3])."""
+    import torch
+    NN = g.N ** g.d
+    X = torch.empty((NN, 9), dtype=torch.float32, device="cuda")
+    T = torch.empty((NN, 3), dtype=torch.float32, device="cuda") if with_targets else None
+    _, tp = _theta(theta)
+    _check(lib().cg_mlp_features(g.handle, tp, float(t_scale), _ptr(X), _ptr(T)))
+    return X, T
 
 
 # Module-level functions named after the C entry points.

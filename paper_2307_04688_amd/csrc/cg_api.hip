@@ -188,6 +188,7 @@ namespace cg {
 const GameConst &game_consts(const cg_game *g) { return g->hc; }
 const Inst &game_inst(const cg_game *g) { return g->inst; }
 int game_precision(const cg_game *g) { return g->precision; }
+hipStream_t game_stream(const cg_game *g) { return g->stream; }
 int set_error(int code, const char *msg)
 {
     g_last_error = msg;

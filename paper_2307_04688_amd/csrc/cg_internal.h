@@ -104,6 +104,7 @@ size_t eval_ws_bytes(int d, const int *n, int precision);
 const GameConst &game_consts(const cg_game *g);
 const Inst &game_inst(const cg_game *g);
 int game_precision(const cg_game *g);
+hipStream_t game_stream(const cg_game *g);
 // Records an error message for cg_last_error(); returns code.
 int set_error(int code, const char *msg);
 
