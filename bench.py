@@ -244,6 +244,48 @@ def run_warm(cg, W, torch, n_train: int = 128, n_test: int = 16, N: int = 24, tr
             "max_rel_V_vs_plain": max(errs) if errs else None}
 
 
+def run_eval(cg, W, torch, steps: int, warmup: int, d: int = 4, N: int = 24, npts: int = 1 << 22):
+    """Standalone evaluation of a d=4, N=24 Chebyshev series (c_k ~ N(0,1)
+    exp(-0.3 sum k), seed 3) at 2^22 points uniform in [-1,1]^4, in FP64, FP32
+    and BF16 with FP32 accumulation.  Algorithmic work: the contraction,
+    2 N^d flops per point."""
+    import numpy as np
+    import oracle
+    coef_h = W.coef_tensor(d, N, seed=3)
+    x_h = W.query_points(d, npts, seed=3)
+    coef = torch.from_numpy(coef_h).cuda()
+    x = torch.from_numpy(x_h).cuda()
+    flops = 2.0 * N ** d * npts
+    out = {"workload": f"Chebyshev series d={d}, N={N} ({N ** d} coefficients) at {npts} points", "flops": flops}
+    res = {}
+    for name, prec, peak in (("fp64", cg.FP64, 78.6), ("fp32", cg.FP32, 157.3), ("bf16", cg.BF16, 2500.0)):
+        for _ in range(warmup):
+            y = cg.chebyshev_eval(coef, x, prec)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            y = cg.chebyshev_eval(coef, x, prec)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / max(steps, 1)
+        res[name] = y.double()
+        out[name] = {"ms": ms, "points_per_s": npts / (ms * 1e-3), "achieved_tflops": flops / (ms * 1e-3) / 1e12,
+                     "peak_tflops": peak, "frac": flops / (ms * 1e-3) / 1e12 / peak}
+    ref = res["fp64"]
+    scale = torch.max(torch.abs(ref)).item()
+    l1 = float(np.abs(coef_h).sum())
+    for name in ("fp32", "bf16"):
+        err = torch.abs(res[name] - ref)
+        out[name].update({"max_abs_err": torch.max(err).item(), "max_rel_err": torch.max(err).item() / scale,
+                          "rms_rel_err": torch.sqrt(torch.mean(err ** 2)).item() / scale,
+                          "max_err_over_sum_abs_c": torch.max(err).item() / l1})
+    idx = np.arange(0, npts, npts // 4096)
+    yo = oracle.eval_points(coef_h, x_h[idx])
+    out["fp64"]["max_rel_err_vs_oracle_4096_points"] = float(np.max(np.abs(ref.cpu().numpy()[idx] - yo)) / scale)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -251,7 +293,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32corr"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="c2", choices=["c2", "batch", "warm"])
+    ap.add_argument("--workload", default="c2", choices=["c2", "batch", "warm", "eval"])
     ap.add_argument("--cpu-steps", type=int, default=6, help="oracle iterations timed for the CPU baseline")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for scaling rocprof byte counters)")
@@ -270,6 +312,9 @@ def main():
     if args.workload == "batch":
         print("bench: ragged batch of 256 games", file=sys.stderr, flush=True)
         print(json.dumps(run_batch(cg, W, torch, args.steps, args.warmup)), flush=True)
+        return
+    if args.workload == "eval":
+        print(json.dumps(run_eval(cg, W, torch, args.steps, args.warmup)), flush=True)
         return
     if args.workload == "warm":
         print(json.dumps(run_warm(cg, W, torch)), flush=True)

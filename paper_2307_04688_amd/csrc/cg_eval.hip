@@ -191,118 +191,224 @@ __global__ __launch_bounds__(256) void k_eval_mfma(const TE *__restrict__ Bp, co
     }
 }
 
-// BF16 evaluation: v_mfma_f32_16x16x32_bf16, lane r + 16 g supplies A[r][8g..8g+7]
-// and B[8g..8g+7][r]; K-steps of 32 over the packed K (padded to 32).
-template <int D, int N4, int NC, int RB>
+// BF16 evaluation as a two-level contraction on v_mfma_f32_16x16x32_bf16
+// (lane r + 16 g supplies A[r][8g..8g+7] and B[8g..8g+7][r]; D[4g+v][r] in
+// element v).  The contracted index space is (o, i): o runs over mode 0 when
+// d >= 3, i over the other contracted modes (mode 1 when d = 4, then mode d-2
+// padded to N4).  The basis products A_q(i) = T(x_q1) T(x_q,d-2) of a chunk of
+// 32 KSC inner indices are rounded to bf16 once and stay in registers for
+// every o; the MFMAs give P_q(o, c) = sum_i A_q(i) C[o, i, c] in f32 and
+// W_q(c) += T_o(x_q0) P_q(o, c), T_o by recurrence in registers.  C streams
+// through LDS one (o, chunk) slab at a time (double-buffered); the per-row
+// basis tables of the inner modes live in LDS.
+struct Bf16Geo {
+    int n_o, n_b, n_l, n_c;  // outer mode, second inner mode (1 if none), mode d-2, last mode
+    int K2, CH;              // inner length n_b * N4, chunks of 32 KSC
+};
+
+// Packed C: fragment-contiguous, ((((o CH + ch) KSC + ks) NCB + c) 4 + g) 16 + col, 8 bf16 each.
+template <int KSC, int NCB>
+__global__ __launch_bounds__(256) void k_pack_bf16(const double *__restrict__ coef, __bf16 *__restrict__ Bp,
+                                                   Bf16Geo gg, int N4)
+{
+    const long long total = (long long)gg.n_o * gg.CH * KSC * NCB * 512;
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= total) return;
+    const int ee = (int)(e & 7), col = (int)((e >> 3) & 15), g = (int)((e >> 7) & 3);
+    long long r = e >> 9;
+    const int c = (int)(r % NCB);
+    r /= NCB;
+    const int ks = (int)(r % KSC);
+    r /= KSC;
+    const int ch = (int)(r % gg.CH);
+    const int o = (int)(r / gg.CH);
+    const int i = (ch * KSC + ks) * 32 + 8 * g + ee;
+    const int colf = c * 16 + col;
+    double v = 0.0;
+    if (i < gg.K2) {
+        const int kb = i / N4, kl = i % N4;
+        if (kl < gg.n_l && colf < gg.n_c)
+            v = coef[(((long long)o * gg.n_b + kb) * gg.n_l + kl) * gg.n_c + colf];
+    }
+    Bp[e] = (__bf16)(float)v;
+}
+
+template <int D, int N4, int NC, int KSC>
 __global__ __launch_bounds__(256) void k_eval_bf16(const __bf16 *__restrict__ Bp, const double *__restrict__ X,
-                                                   float *__restrict__ out, long long npts, int n0, int n1,
-                                                   int nlast, long long Kpad)
+                                                   float *__restrict__ out, long long npts, Bf16Geo gg)
 {
     constexpr int NCB = NC / 16;
-    constexpr int ROWS_W = RB * 16;
-    constexpr int ROWS_B = 4 * ROWS_W;
+    constexpr int RB = 2;
+    constexpr int ROWS_B = 4 * RB * 16;           // 128 points per block
+    constexpr int LDT = 36;                       // basis table stride (floats; 16-byte rows)
+    constexpr int SLAB = KSC * NCB * 512;         // bf16 per (o, chunk) slab
+    constexpr int SLAB16 = SLAB / 8;              // 16-byte units per slab
+    constexpr int PF = (SLAB16 + 255) / 256;
     constexpr int LDW = NC + 1;
-    __shared__ double Wl[ROWS_B * LDW];
+    static_assert(ROWS_B * LDW <= ROWS_B * LDT, "W staging aliases the mode-l table");
+    __shared__ __attribute__((aligned(16))) float Tl[ROWS_B * LDT];
+    __shared__ __attribute__((aligned(16))) float Tb[D == 4 ? ROWS_B * LDT : 4];
+    __shared__ __attribute__((aligned(16))) __bf16 Bs[2 * SLAB];
 
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int r16 = lane & 15, g = lane >> 4;
-    const long long row0 = (long long)blockIdx.x * ROWS_B + wave * ROWS_W;
+    const long long q0 = (long long)blockIdx.x * ROWS_B;
 
-    // per row: full basis of mode D-2 (float) and outer coordinates
-    float Tl[RB][N4];
-    double xo[RB][2];
-#pragma unroll
-    for (int rb = 0; rb < RB; ++rb) {
-        long long q = row0 + rb * 16 + r16;
+    // ---- per-row basis tables (FP64 recurrences, stored as binary32) ----
+    {
+        const int r = tid & (ROWS_B - 1);
+        long long q = q0 + r;
         q = q < npts ? q : npts - 1;
         const double *xq = X + q * D;
-        xo[rb][0] = D >= 3 ? xq[0] : 0.0;
-        xo[rb][1] = D >= 4 ? xq[1] : 0.0;
-        const double xl = xq[D - 2];
-        double tm1 = 1.0, t0 = xl;
-#pragma unroll
-        for (int k = 0; k < N4; ++k) {
-            double tk;
-            if (k == 0) tk = 1.0;
-            else if (k == 1) tk = xl;
-            else { tk = 2.0 * xl * t0 - tm1; tm1 = t0; t0 = tk; }
-            Tl[rb][k] = (float)tk;
+        if (tid < ROWS_B) {
+            const double xl = xq[D - 2];
+            double tm = 1.0, tc = xl;
+            Tl[r * LDT] = 1.0f;
+            for (int k = 1; k < N4; ++k) {
+                Tl[r * LDT + k] = (float)tc;
+                const double tn = 2.0 * xl * tc - tm;
+                tm = tc;
+                tc = tn;
+            }
+            if (D == 4) {
+                const double xb = xq[1];
+                tm = 1.0;
+                tc = xb;
+                Tb[r * LDT] = 1.0f;
+                for (int k = 1; k < gg.n_b; ++k) {
+                    Tb[r * LDT + k] = (float)tc;
+                    const double tn = 2.0 * xb * tc - tm;
+                    tm = tc;
+                    tc = tn;
+                }
+            }
         }
     }
-
-    f32x4 acc[RB][NCB];
+    // outer coordinate of the accumulator rows 4g + v of each row block
+    float xo4[RB][4];
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-        for (int c = 0; c < NCB; ++c) acc[rb][c] = f32x4{0.f, 0.f, 0.f, 0.f};
-
-    // K index kk = oc * N4 + kl; a K-step covers 32 consecutive kk.  Outer
-    // factors F(oc) are recomputed per element from per-row recurrence tables.
-    const int n_outer = (D == 2) ? 1 : (D == 3 ? n0 : n0 * n1);
-    const int nsteps = (int)(Kpad / 32);
-    for (int st = 0; st < nsteps; ++st) {
-        const long long kbase = (long long)st * 32 + 8 * g;
-        bf16x8 bfr[NCB];
-#pragma unroll
-        for (int c = 0; c < NCB; ++c) {
-#pragma unroll
-            for (int e = 0; e < 8; ++e) bfr[c][e] = Bp[(kbase + e) * NC + c * 16 + r16];
+        for (int v = 0; v < 4; ++v) {
+            long long q = q0 + wave * 32 + rb * 16 + 4 * g + v;
+            q = q < npts ? q : npts - 1;
+            xo4[rb][v] = D >= 3 ? (float)X[q * D] : 0.0f;
         }
+    float Fm[RB][4], Fc[RB][4];  // T_{o-1}, T_o at those rows
+
+    const uint4 *Bg = reinterpret_cast<const uint4 *>(Bp);
+    uint4 pf[PF];
+    auto load_slab = [&](int s) {  // loop order (chunk, o); memory order (o, chunk)
+        const int ch = s / gg.n_o, o = s - ch * gg.n_o;
+        const long long base = ((long long)o * gg.CH + ch) * SLAB16;
 #pragma unroll
-        for (int rb = 0; rb < RB; ++rb) {
-            bf16x8 a;
+        for (int k = 0; k < PF; ++k) {
+            const int u = tid + k * 256;
+            if (u < SLAB16) pf[k] = Bg[base + u];
+        }
+    };
+    auto store_slab = [&](int buf) {
+        uint4 *dst = reinterpret_cast<uint4 *>(Bs + buf * SLAB);
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const long long kk = kbase + e;
-                const int kl = (int)(kk % N4);
-                const int oc = (int)(kk / N4);
-                float F = 1.0f;
-                if (D >= 3 && oc < n_outer) {
-                    // outer factor by direct recurrence (short: n0, n1 <= 32)
-                    int ka = (D == 3) ? oc : oc / n1;
-                    double x0 = xo[rb][0], tp = 1.0, tc = x0, T0 = 1.0;
-                    if (ka == 0) T0 = 1.0; else if (ka == 1) T0 = x0;
-                    else { for (int k = 2; k <= ka; ++k) { const double tn = 2.0 * x0 * tc - tp; tp = tc; tc = tn; } T0 = tc; }
-                    double Ff = T0;
-                    if (D == 4) {
-                        const int kb = oc % n1;
-                        double x1 = xo[rb][1], sp = 1.0, sc = x1, T1 = 1.0;
-                        if (kb == 0) T1 = 1.0; else if (kb == 1) T1 = x1;
-                        else { for (int k = 2; k <= kb; ++k) { const double sn = 2.0 * x1 * sc - sp; sp = sc; sc = sn; } T1 = sc; }
-                        Ff *= T1;
+        for (int k = 0; k < PF; ++k) {
+            const int u = tid + k * 256;
+            if (u < SLAB16) dst[u] = pf[k];
+        }
+    };
+
+    f32x4 W[RB][NCB];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int c = 0; c < NCB; ++c) W[rb][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+    bf16x8 a[RB][KSC];
+
+    const int nslab = gg.CH * gg.n_o;
+    load_slab(0);
+    store_slab(0);
+    __syncthreads();
+    for (int s = 0; s < nslab; ++s) {
+        const int ch = s / gg.n_o, o = s - ch * gg.n_o;
+        if (o == 0) {  // basis products of this chunk, rounded to bf16 once
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) {
+                const int r = wave * 32 + rb * 16 + r16;
+#pragma unroll
+                for (int ks = 0; ks < KSC; ++ks)
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const int i0 = (ch * KSC + ks) * 32 + 8 * g + 4 * h;
+                        float4 t = make_float4(0.f, 0.f, 0.f, 0.f);
+                        float tb = 0.f;
+                        if (i0 < gg.K2) {
+                            const int kb = i0 / N4, kl0 = i0 - (i0 / N4) * N4;
+                            t = *reinterpret_cast<const float4 *>(Tl + r * LDT + kl0);
+                            tb = D == 4 ? Tb[r * LDT + kb] : 1.0f;
+                        }
+                        a[rb][ks][4 * h + 0] = (__bf16)(tb * t.x);
+                        a[rb][ks][4 * h + 1] = (__bf16)(tb * t.y);
+                        a[rb][ks][4 * h + 2] = (__bf16)(tb * t.z);
+                        a[rb][ks][4 * h + 3] = (__bf16)(tb * t.w);
                     }
-                    F = (float)Ff;
-                } else if (oc >= n_outer) {
-                    F = 0.0f;
-                }
-                float tl = 0.0f;
+            }
+        }
+        const __bf16 *cb = Bs + (s & 1) * SLAB;
+        const bool more = s + 1 < nslab;
+        if (more) load_slab(s + 1);
+        f32x4 P[RB][NCB];
 #pragma unroll
-                for (int k = 0; k < N4; ++k)
-                    if (k == kl) tl = Tl[rb][k];
-                a[e] = (__bf16)(F * tl);
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int c = 0; c < NCB; ++c) P[rb][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < KSC; ++ks) {
+#pragma unroll
+            for (int c = 0; c < NCB; ++c) {
+                const bf16x8 b = *reinterpret_cast<const bf16x8 *>(cb + ((ks * NCB + c) * 64 + lane) * 8);
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb)
+                    P[rb][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[rb][ks], b, P[rb][c], 0, 0, 0);
+            }
+        }
+        // outer factor T_o(x_q0) by the three-term recurrence, restarted per chunk
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                float t;
+                if (D < 3 || o == 0) t = 1.0f;
+                else if (o == 1) t = xo4[rb][v];
+                else t = 2.0f * xo4[rb][v] * Fc[rb][v] - Fm[rb][v];
+                Fm[rb][v] = o == 0 ? 0.0f : Fc[rb][v];
+                Fc[rb][v] = t;
             }
 #pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
             for (int c = 0; c < NCB; ++c)
-                acc[rb][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bfr[c], acc[rb][c], 0, 0, 0);
-        }
+#pragma unroll
+                for (int v = 0; v < 4; ++v) W[rb][c][v] = fmaf(Fc[rb][v], P[rb][c][v], W[rb][c][v]);
+        if (more) store_slab((s + 1) & 1);
+        __syncthreads();
     }
 
+    // ---- W rows to LDS (over the mode-l table), Clenshaw along the last mode ----
+    float *Wl = Tl;
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
         for (int c = 0; c < NCB; ++c)
 #pragma unroll
-            for (int v = 0; v < 4; ++v)
-                Wl[(wave * ROWS_W + rb * 16 + 4 * g + v) * LDW + c * 16 + r16] = (double)acc[rb][c][v];
+            for (int v = 0; v < 4; ++v) Wl[(wave * 32 + rb * 16 + 4 * g + v) * LDW + c * 16 + r16] = W[rb][c][v];
     __syncthreads();
-
-    for (int row = tid; row < ROWS_B; row += 256) {
-        const long long q = (long long)blockIdx.x * ROWS_B + row;
-        if (q >= npts) continue;
-        double w[NC];
+    if (tid < ROWS_B) {
+        const long long q = q0 + tid;
+        if (q < npts) {
+            double w[NC];
 #pragma unroll
-        for (int k = 0; k < NC; ++k) w[k] = Wl[row * LDW + k];
-        out[q] = (float)clenshaw(w, X[q * D + D - 1]);  // columns >= nlast are zero
+            for (int k = 0; k < NC; ++k) w[k] = (double)Wl[tid * LDW + k];
+            out[q] = (float)clenshaw(w, X[q * D + D - 1]);  // columns >= n_c are zero
+        }
     }
 }
 
@@ -338,14 +444,46 @@ static long long eval_K(int d, const int *n, int N4)
     return K;
 }
 
+// Geometry of the BF16 operand: outer mode, inner modes, chunking.
+static Bf16Geo bf16_geo(int d, const int *n, int &ksc)
+{
+    Bf16Geo gg;
+    const int N4 = round4(n[d - 2]);
+    gg.n_o = d >= 3 ? n[0] : 1;
+    gg.n_b = d == 4 ? n[1] : 1;
+    gg.n_l = n[d - 2];
+    gg.n_c = n[d - 1];
+    gg.K2 = gg.n_b * N4;
+    const int steps = (gg.K2 + 31) / 32;
+    // fewest padded steps, counting one step of overhead per chunk
+    const int cand[4] = {6, 4, 2, 1};
+    int best = 1 << 30;
+    ksc = 1;
+    for (int c : cand) {
+        const int ch = (steps + c - 1) / c;
+        const int cost = ch * c + ch;
+        if (d == 4 && cost < best) {
+            best = cost;
+            ksc = c;
+        }
+    }
+    if (d < 4) ksc = 1;
+    gg.CH = (steps + ksc - 1) / ksc;
+    return gg;
+}
+
 size_t eval_ws_bytes(int d, const int *n, int precision)
 {
     if (d < 2) return 0;
     const int N4 = round4(n[d - 2]);
     const int NC = n[d - 1] <= 16 ? 16 : 32;
-    long long K = eval_K(d, n, N4);
-    size_t es = precision == CG_FP64 ? 8 : (precision == CG_FP32 ? 4 : 2);
-    if (precision == CG_BF16) K = (K + 31) / 32 * 32;
+    if (precision == CG_BF16) {
+        int ksc;
+        const Bf16Geo gg = bf16_geo(d, n, ksc);
+        return (size_t)gg.n_o * gg.CH * ksc * (NC / 16) * 512 * 2 + 256;
+    }
+    const long long K = eval_K(d, n, N4);
+    const size_t es = precision == CG_FP64 ? 8 : 4;
     return (size_t)(K * NC) * es + 256;
 }
 
@@ -367,21 +505,43 @@ static hipError_t launch_eval_dn(const void *Bp, const double *x, TO *out, long 
     return hipGetLastError();
 }
 
-template <int D, int N4>
-static hipError_t launch_eval_bf16_dn(const void *Bp, const double *x, float *out, long long npts, const int *n,
-                                      long long Kpad, hipStream_t s)
+template <int D, int N4, int NC, int KSC>
+static hipError_t launch_bf16_k(const double *coef, void *ws, const double *x, float *out, long long npts,
+                                const Bf16Geo &gg, hipStream_t s)
 {
-    constexpr int RB = 2;
-    const int rows_b = 4 * RB * 16;
-    const unsigned blocks = (unsigned)((npts + rows_b - 1) / rows_b);
-    const int n0 = D >= 3 ? n[0] : 1, n1 = D >= 4 ? n[1] : 1;
-    if (n[D - 1] <= 16)
-        hipLaunchKernelGGL((k_eval_bf16<D, N4, 16, RB>), dim3(blocks), dim3(256), 0, s, (const __bf16 *)Bp, x, out,
-                           npts, n0, n1, n[D - 1], Kpad);
-    else
-        hipLaunchKernelGGL((k_eval_bf16<D, N4, 32, RB>), dim3(blocks), dim3(256), 0, s, (const __bf16 *)Bp, x, out,
-                           npts, n0, n1, n[D - 1], Kpad);
+    const long long total = (long long)gg.n_o * gg.CH * KSC * (NC / 16) * 512;
+    hipLaunchKernelGGL((k_pack_bf16<KSC, NC / 16>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, coef,
+                       (__bf16 *)ws, gg, N4);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const unsigned blocks = (unsigned)((npts + 127) / 128);
+    hipLaunchKernelGGL((k_eval_bf16<D, N4, NC, KSC>), dim3(blocks), dim3(256), 0, s, (const __bf16 *)ws, x, out,
+                       npts, gg);
     return hipGetLastError();
+}
+
+template <int D, int N4>
+static hipError_t launch_eval_bf16_dn(const double *coef, void *ws, const double *x, float *out, long long npts,
+                                      const int *n, hipStream_t s)
+{
+    int ksc;
+    const Bf16Geo gg = bf16_geo(D, n, ksc);
+    if (n[D - 1] <= 16) {
+        if (D < 4) return launch_bf16_k<D, N4, 16, 1>(coef, ws, x, out, npts, gg, s);
+        switch (ksc) {
+            case 6: return launch_bf16_k<D, N4, 16, 6>(coef, ws, x, out, npts, gg, s);
+            case 4: return launch_bf16_k<D, N4, 16, 4>(coef, ws, x, out, npts, gg, s);
+            case 2: return launch_bf16_k<D, N4, 16, 2>(coef, ws, x, out, npts, gg, s);
+            default: return launch_bf16_k<D, N4, 16, 1>(coef, ws, x, out, npts, gg, s);
+        }
+    }
+    if (D < 4) return launch_bf16_k<D, N4, 32, 1>(coef, ws, x, out, npts, gg, s);
+    switch (ksc) {
+        case 6: return launch_bf16_k<D, N4, 32, 6>(coef, ws, x, out, npts, gg, s);
+        case 4: return launch_bf16_k<D, N4, 32, 4>(coef, ws, x, out, npts, gg, s);
+        case 2: return launch_bf16_k<D, N4, 32, 2>(coef, ws, x, out, npts, gg, s);
+        default: return launch_bf16_k<D, N4, 32, 1>(coef, ws, x, out, npts, gg, s);
+    }
 }
 
 #define CG_N4_SWITCH(N4v, CALL)                  \
@@ -398,16 +558,23 @@ static hipError_t launch_eval_bf16_dn(const void *Bp, const double *x, float *ou
 
 template <int D>
 static hipError_t launch_eval_d(const void *Bp, const double *x, void *out, long long npts, const int *n,
-                                int precision, long long Kpad, hipStream_t s)
+                                int precision, hipStream_t s)
 {
     const int N4 = round4(n[D - 2]);
     if (precision == CG_FP64) {
         CG_N4_SWITCH(N4, return (launch_eval_dn<double, double, D, N4c>(Bp, x, (double *)out, npts, n, s)))
-    } else if (precision == CG_FP32) {
-        CG_N4_SWITCH(N4, return (launch_eval_dn<float, float, D, N4c>(Bp, x, (float *)out, npts, n, s)))
     } else {
-        CG_N4_SWITCH(N4, return (launch_eval_bf16_dn<D, N4c>(Bp, x, (float *)out, npts, n, Kpad, s)))
+        CG_N4_SWITCH(N4, return (launch_eval_dn<float, float, D, N4c>(Bp, x, (float *)out, npts, n, s)))
     }
+    return hipErrorInvalidValue;
+}
+
+template <int D>
+static hipError_t launch_eval_bf16_d(const double *coef, void *ws, const double *x, void *out, long long npts,
+                                     const int *n, hipStream_t s)
+{
+    const int N4 = round4(n[D - 2]);
+    CG_N4_SWITCH(N4, return (launch_eval_bf16_dn<D, N4c>(coef, ws, x, (float *)out, npts, n, s)))
     return hipErrorInvalidValue;
 }
 
@@ -425,28 +592,32 @@ hipError_t launch_eval(int d, const int *n, const double *coef, const double *x,
                                precision);
         return hipGetLastError();
     }
+    if (ws_bytes < eval_ws_bytes(d, n, precision)) return hipErrorInvalidValue;
+    if (precision == CG_BF16) {
+        switch (d) {
+            case 2: return launch_eval_bf16_d<2>(coef, ws, x, out, npts, n, s);
+            case 3: return launch_eval_bf16_d<3>(coef, ws, x, out, npts, n, s);
+            case 4: return launch_eval_bf16_d<4>(coef, ws, x, out, npts, n, s);
+        }
+        return hipErrorInvalidValue;
+    }
     const int N4 = round4(n[d - 2]);
     const int NC = n[d - 1] <= 16 ? 16 : 32;
-    long long K = eval_K(d, n, N4);
-    long long Kpad = precision == CG_BF16 ? (K + 31) / 32 * 32 : K;
-    if (ws_bytes < eval_ws_bytes(d, n, precision)) return hipErrorInvalidValue;
+    const long long K = eval_K(d, n, N4);
     const int nn[4] = {n[0], d > 1 ? n[1] : 1, d > 2 ? n[2] : 1, d > 3 ? n[3] : 1};
-    const unsigned pb = (unsigned)((Kpad * NC + 255) / 256);
+    const unsigned pb = (unsigned)((K * NC + 255) / 256);
     if (precision == CG_FP64)
         hipLaunchKernelGGL(k_pack_eval<double>, dim3(pb), dim3(256), 0, s, coef, (double *)ws, d, nn[0], nn[1], nn[2],
-                           nn[3], N4, NC, K, Kpad);
-    else if (precision == CG_FP32)
-        hipLaunchKernelGGL(k_pack_eval<float>, dim3(pb), dim3(256), 0, s, coef, (float *)ws, d, nn[0], nn[1], nn[2],
-                           nn[3], N4, NC, K, Kpad);
+                           nn[3], N4, NC, K, K);
     else
-        hipLaunchKernelGGL(k_pack_eval<__bf16>, dim3(pb), dim3(256), 0, s, coef, (__bf16 *)ws, d, nn[0], nn[1],
-                           nn[2], nn[3], N4, NC, K, Kpad);
+        hipLaunchKernelGGL(k_pack_eval<float>, dim3(pb), dim3(256), 0, s, coef, (float *)ws, d, nn[0], nn[1], nn[2],
+                           nn[3], N4, NC, K, K);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     switch (d) {
-        case 2: return launch_eval_d<2>(ws, x, out, npts, n, precision, Kpad, s);
-        case 3: return launch_eval_d<3>(ws, x, out, npts, n, precision, Kpad, s);
-        case 4: return launch_eval_d<4>(ws, x, out, npts, n, precision, Kpad, s);
+        case 2: return launch_eval_d<2>(ws, x, out, npts, n, precision, s);
+        case 3: return launch_eval_d<3>(ws, x, out, npts, n, precision, s);
+        case 4: return launch_eval_d<4>(ws, x, out, npts, n, precision, s);
     }
     return hipErrorInvalidValue;
 }

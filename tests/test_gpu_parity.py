@@ -113,6 +113,27 @@ def test_eval_low_precision_within_bound(cg, orc, prec, u_in, shape):
     say("  max err", err.max(), "bound", bound, "ratio", err.max() / bound)
 
 
+@pytest.mark.parametrize("shape,npts", [((5, 4), 999), ((17, 20), 130), ((6, 7, 9), 1000), ((3, 5, 4, 6), 1500),
+                                        ((20, 13, 30, 7), 517), ((9, 31, 22, 17), 257), ((32, 32, 32, 32), 300)])
+def test_eval_bf16_ragged_within_bound(cg, orc, shape, npts):
+    """BF16 evaluation on uneven mode sizes (chunked inner index space,
+    padded last modes, ragged point counts) within the same a-priori bound."""
+    say("eval bf16", shape, npts)
+    d = len(shape)
+    c = W.coef_tensor(d, max(shape), seed=19)[tuple(slice(0, s) for s in shape)].copy()
+    x = W.query_points(d, npts, seed=19)
+    out = cg.chebyshev_eval(dev(c), dev(x), cg.BF16).cpu().numpy().astype(np.float64)
+    ref = orc.eval_points(c, x)
+    K = int(np.prod(shape[:-1]))
+    u32, u_in = 2.0 ** -24, 2.0 ** -8
+    gamma = (K + 1) * u32 / (1 - (K + 1) * u32)
+    bound = (2 * u_in + u_in * u_in + gamma) * np.sum(np.abs(c)) + 1e-30
+    err = np.abs(out - ref)
+    assert np.all(err <= bound), (err.max(), bound)
+    # and far from trivially so: the error is at the bf16 rounding level of the largest terms
+    assert err.max() <= 0.05 * bound or err.max() < 1e-2 * np.max(np.abs(ref))
+
+
 # ---------------------------------------------------------------- game step
 
 def _gpu_game(cg, g, prec=None):
