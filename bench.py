@@ -77,6 +77,38 @@ def err_vs_reference(G, g):
             "source": "oracle reference at 512 sampled (player, node) pairs"}
 
 
+def solve_rate(cg, torch, g, prec, time_steps: int, steps: int, warmup: int):
+    """Solves/s of one game from the zero terminal value over `time_steps`
+    iterations, with the contraction kernel's roofline from HIP events
+    recorded around each of its launches on the game's stream."""
+    name = "fp64" if prec == cg.FP64 else "fp32corr"
+    print(f"bench: d={g.d} N={g.N} steps={time_steps} precision={name}", file=sys.stderr, flush=True)
+    G = cg.ChebGame(g, prec)
+    for _ in range(warmup):
+        G.reset()
+        G.solve(time_steps)
+    torch.cuda.synchronize()
+    G.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        G.reset()
+        G.solve(time_steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kernel_ms, launches = G.profile(False)
+    ms_per_solve = (t1 - t0) * 1e3 / max(steps, 1)
+    # algorithmic contraction flops per launch: d players * 2 N^(2d)
+    flops_launch = g.d * 2.0 * float(g.N) ** (2 * g.d)
+    avg_ms = kernel_ms / max(launches, 1)
+    achieved = flops_launch / (avg_ms * 1e-3) / 1e12
+    peak = PEAK["fp64"] if prec == cg.FP64 else PEAK["fp32"]
+    kname = "k_contract_f64" if prec == cg.FP64 else "k_contract_corr"
+    roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+            "traffic": measured_traffic(f"{kname} d={g.d} N={g.N}"), "kernel": kname,
+            "avg_launch_ms": avg_ms, "launches": launches, "flops_per_launch": flops_launch}
+    return {"solves_per_s": 1e3 / ms_per_solve, "ms_per_solve": ms_per_solve, "roofline": roof, "game": G}
+
+
 def run_batch(cg, W, torch, steps: int, warmup: int, count: int = 256, time_steps: int = 150):
     """Ragged batch: `count` games, d in {2,3}, N in {12,16,24,32}, seeded
     parameters per instance, `time_steps` iterations each from V=0.  The
@@ -291,9 +323,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5, help="timed solves")
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32corr"])
+    ap.add_argument("--precision", default="fp32corr", choices=["fp64", "fp32corr"],
+                    help="path reported as value; the other is timed beside it")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="c2", choices=["c2", "batch", "warm", "eval"])
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "batch", "warm", "eval"])
     ap.add_argument("--cpu-steps", type=int, default=6, help="oracle iterations timed for the CPU baseline")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for scaling rocprof byte counters)")
@@ -319,39 +352,23 @@ def main():
     if args.workload == "warm":
         print(json.dumps(run_warm(cg, W, torch)), flush=True)
         return
+    if args.workload == "c3":
+        g = W.config_game("C3")
+        out = {"workload": "LQ pollution game d=4 players, N=24 nodes/dim (331776 nodes), 100 value-iteration "
+                           "steps from zero terminal value, seed-3 parameters"}
+        for name, prec in (("fp64", cg.FP64), ("fp32corr", cg.FP32_CORR)):
+            out[name] = solve_rate(cg, torch, g, prec, 100, args.steps, args.warmup)
+            out[name].pop("game")
+        print(json.dumps(out), flush=True)
+        return
+
     g = W.config_game("C2")
-    prec = cg.FP64 if args.precision == "fp64" else cg.FP32_CORR
-    print(f"bench: d={g.d} N={g.N} steps={TIME_STEPS} precision={args.precision}", file=sys.stderr, flush=True)
-    G = cg.ChebGame(g, prec)
-    for _ in range(args.warmup):
-        G.reset()
-        G.solve(TIME_STEPS)
-    torch.cuda.synchronize()
-    G.profile(True)
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        G.reset()
-        G.solve(TIME_STEPS)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    kernel_ms, launches = G.profile(False)
-    ms_per_solve = (t1 - t0) * 1e3 / max(args.steps, 1)
-    solves_per_s = 1e3 / ms_per_solve
-    NN = g.N ** g.d
-    node_evals = solves_per_s * TIME_STEPS * g.d * NN
-
-    # roofline of the dominant kernel (fused contraction step): algorithmic
-    # contraction flops per launch = d players * 2 N^(2d)
-    flops_launch = g.d * 2.0 * float(g.N) ** (2 * g.d)
-    avg_ms = kernel_ms / max(launches, 1)
-    achieved = flops_launch / (avg_ms * 1e-3) / 1e12
-    peak = PEAK["fp64"] if prec == cg.FP64 else PEAK["fp32"]
-    kname = "k_contract_f64" if prec == cg.FP64 else "k_contract_corr"
-    roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-            "traffic": measured_traffic(f"{kname} d={g.d} N={g.N}"), "kernel": kname,
-            "avg_launch_ms": avg_ms, "launches": launches, "flops_per_launch": flops_launch}
-
-    err = err_vs_reference(G, g)
+    main_prec = cg.FP64 if args.precision == "fp64" else cg.FP32_CORR
+    other = cg.FP32_CORR if main_prec == cg.FP64 else cg.FP64
+    res = solve_rate(cg, torch, g, main_prec, TIME_STEPS, args.steps, args.warmup)
+    res_other = solve_rate(cg, torch, g, other, TIME_STEPS, args.steps, args.warmup)
+    err = err_vs_reference(res.pop("game"), g)
+    err_other = err_vs_reference(res_other.pop("game"), g)
 
     if args.copy_calibration:
         a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
@@ -360,13 +377,20 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
 
-    out = {"metric": METRIC, "value": solves_per_s, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
-           "warmup": args.warmup, "ms_per_step": ms_per_solve, "higher_is_better": True, "scaling": "weak",
-           "vs_baseline": None, "dtype": "f64" if prec == cg.FP64 else "f32+f64", "data": "synthetic",
+    NN = g.N ** g.d
+    name = "fp64" if main_prec == cg.FP64 else "fp32corr"
+    oname = "fp32corr" if main_prec == cg.FP64 else "fp64"
+    out = {"metric": METRIC, "value": res["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": res["ms_per_solve"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64" if main_prec == cg.FP64 else "f32+f64", "data": "synthetic",
            "config": {"workload": "LQ pollution game d=3 players, N=32 nodes/dim (32768 nodes), 200 value-"
                                   "iteration steps from zero terminal value, seed-2 parameters",
-                      "d": g.d, "N": g.N, "time_steps": TIME_STEPS, "precision": args.precision},
-           "node_evals_per_s": node_evals, "roofline": roof, "err_vs_oracle": err}
+                      "d": g.d, "N": g.N, "time_steps": TIME_STEPS, "precision": name},
+           "node_evals_per_s": res["solves_per_s"] * TIME_STEPS * g.d * NN, "roofline": res["roofline"],
+           "err_vs_oracle": err,
+           oname: {"solves_per_s": res_other["solves_per_s"], "ms_per_solve": res_other["ms_per_solve"],
+                   "roofline": res_other["roofline"], "err_vs_oracle": err_other},
+           f"{name}_vs_{oname}": res["solves_per_s"] / res_other["solves_per_s"]}
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(g, args.cpu_steps)

@@ -173,7 +173,8 @@ struct cg_game {
     hipStream_t stream;
     int precision;
     StepBuffers b;
-    Inst inst;          // host copy of the one-entry device table
+    InstPtrs inst;      // device pointers of the game
+    Inst entry;         // host copy of the one-entry device table
     long long launched; // iterations queued (including no-ops after convergence)
     bool prof;                     // record events around the contraction kernel
     std::vector<hipEvent_t> evs;   // pairs (begin, end), one pair per profiled launch
@@ -186,7 +187,25 @@ struct cg_game {
 
 namespace cg {
 const GameConst &game_consts(const cg_game *g) { return g->hc; }
-const Inst &game_inst(const cg_game *g) { return g->inst; }
+const InstPtrs &game_inst(const cg_game *g) { return g->inst; }
+Inst inst_offsets(const InstPtrs &p, const void *table_dev)
+{
+    const char *b = (const char *)table_dev;
+    auto off = [b](const void *q) -> long long { return q ? (long long)((const char *)q - b) : 0; };
+    Inst e;
+    e.gc = off(p.gc);
+    e.st = off(p.st);
+    e.V = off(p.V);
+    e.U = off(p.U);
+    e.coef = off(p.coef);
+    e.tmp = off(p.tmp);
+    e.Bp = off(p.Bp);
+    e.W = off(p.W);
+    e.Bp32 = off(p.Bp32);
+    e.E = off(p.E);
+    e.G = off(p.G);
+    return e;
+}
 int game_precision(const cg_game *g) { return g->precision; }
 hipStream_t game_stream(const cg_game *g) { return g->stream; }
 int set_error(int code, const char *msg)
@@ -386,7 +405,7 @@ int cg_init_game(const cg_game_desc *g, int precision, void *ws_dev, size_t ws_b
     b.tab = (const Inst *)(G->ws + L.tab);
     b.count = 1;
     b.rb = 2;
-    Inst &hi = G->inst;
+    InstPtrs &hi = G->inst;
     hi.gc = b.gc;
     hi.st = b.status;
     hi.V = b.V;
@@ -402,7 +421,8 @@ int cg_init_game(const cg_game_desc *g, int precision, void *ws_dev, size_t ws_b
     G->ev_used = 0;
 
     hipError_t e = hipMemcpyAsync(G->ws + L.gc, &hc, sizeof hc, hipMemcpyHostToDevice, G->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(G->ws + L.tab, &G->inst, sizeof(Inst), hipMemcpyHostToDevice, G->stream);
+    G->entry = inst_offsets(G->inst, G->ws + L.tab);
+    if (e == hipSuccess) e = hipMemcpyAsync(G->ws + L.tab, &G->entry, sizeof(Inst), hipMemcpyHostToDevice, G->stream);
     if (e == hipSuccess) {
         hipLaunchKernelGGL(k_fill_state, dim3(256), dim3(256), 0, G->stream, b.V, b.U, b.gc, b.status);
         e = hipGetLastError();

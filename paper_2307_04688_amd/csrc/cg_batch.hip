@@ -41,8 +41,9 @@ __global__ void k_batch_arm(const Inst *__restrict__ tab, int count, double tol,
 {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= count) return;
-    GameConst *gc = const_cast<GameConst *>(tab[g].gc);
-    GameStatus *st = tab[g].st;
+    const InstView I = inst_view(tab, g);
+    GameConst *gc = const_cast<GameConst *>(I.gc);
+    GameStatus *st = I.st;
     gc->tol = tol;
     st->converged = 0;
     st->nonfinite = 0;
@@ -55,7 +56,7 @@ __global__ void k_batch_gather(const Inst *__restrict__ tab, int count, StatusCo
 {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= count) return;
-    const GameStatus *st = tab[g].st;
+    const GameStatus *st = inst_view(tab, g).st;
     out[g].last_res = st->last_res;
     out[g].converged = st->converged;
     out[g].steps_done = st->steps_done;
@@ -68,7 +69,7 @@ __global__ void k_batch_reset(const Inst *__restrict__ tab, int count)
 {
     const int g = blockIdx.y;
     if (g >= count) return;
-    const Inst &I = tab[g];
+    const InstView I = inst_view(tab, g);
     const GameConst *gc = I.gc;
     const long long n = (long long)gc->d * gc->NN;
     for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < 2 * n;
@@ -237,14 +238,14 @@ int cg_batch_create(cg_game *const *games, int32_t count, void *ws_dev, size_t w
     for (Group &G : B->groups) {
         G.tab_off = off;
         std::vector<Inst> t;
-        for (int m : G.members) t.push_back(game_inst(games[m]));
+        for (int m : G.members) t.push_back(inst_offsets(game_inst(games[m]), B->ws + G.tab_off));
         off = align256(off + sizeof(Inst) * t.size());
         uploads.push_back({G.tab_off, t});
     }
     B->all_tab_off = off;
     {
         std::vector<Inst> t;
-        for (int i = 0; i < count; ++i) t.push_back(game_inst(games[i]));
+        for (int i = 0; i < count; ++i) t.push_back(inst_offsets(game_inst(games[i]), B->ws + off));
         uploads.push_back({off, t});
         off = align256(off + sizeof(Inst) * t.size());
     }

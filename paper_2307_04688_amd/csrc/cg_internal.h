@@ -59,10 +59,8 @@ hipError_t launch_transform_mode(const double *in, double *out, int d, const int
 hipError_t run_transform(int d, const int *n, const double *vals, double *coef, long long batch,
                          hipStream_t s);
 
-// Device pointers of one game instance.  Step kernels take a table of
-// these and serve tab[blockIdx.x / blocks_per_instance], so that one launch
-// covers every instance of a group with the same d and N.
-struct Inst {
+// Device pointers of one game instance (host side).
+struct InstPtrs {
     const GameConst *gc;
     GameStatus *st;
     double *V, *U;           // [2][d][NN] each
@@ -72,6 +70,43 @@ struct Inst {
     float *Bp32;             // packed operand (binary32, FP32_CORR)
     double *E, *G;           // FP32_CORR tensors
 };
+
+// Entry of a device table of instances: the same pointers as byte offsets
+// from the table's own address.  Step kernels take a table and serve entry
+// blockIdx.x / blocks_per_instance, so that one launch covers every instance
+// of a group with the same d and N.  Pointers rebuilt from the table (a
+// kernel argument) plus an offset are known to the compiler to be global
+// memory, so loads and stores through them are global (not flat) accesses.
+struct Inst {
+    long long gc, st, V, U, coef, tmp, Bp, W, Bp32, E, G;
+};
+Inst inst_offsets(const InstPtrs &p, const void *table_dev);
+
+struct InstView {
+    const GameConst *gc;
+    GameStatus *st;
+    double *V, *U, *coef, *tmp, *Bp, *W;
+    float *Bp32;
+    double *E, *G;
+};
+__device__ __forceinline__ InstView inst_view(const Inst *tab, int k)
+{
+    const Inst &e = tab[k];
+    const char *b = (const char *)tab;
+    InstView v;
+    v.gc = (const GameConst *)(b + e.gc);
+    v.st = (GameStatus *)(b + e.st);
+    v.V = (double *)(b + e.V);
+    v.U = (double *)(b + e.U);
+    v.coef = (double *)(b + e.coef);
+    v.tmp = (double *)(b + e.tmp);
+    v.Bp = (double *)(b + e.Bp);
+    v.W = (double *)(b + e.W);
+    v.Bp32 = (float *)(b + e.Bp32);
+    v.E = (double *)(b + e.E);
+    v.G = (double *)(b + e.G);
+    return v;
+}
 
 // One value-iteration step of a game (all kernels of Steps 1-4).
 struct StepBuffers {
@@ -102,7 +137,7 @@ size_t eval_ws_bytes(int d, const int *n, int precision);
 
 // Accessors of a game handle for the batch code (defined with the handle).
 const GameConst &game_consts(const cg_game *g);
-const Inst &game_inst(const cg_game *g);
+const InstPtrs &game_inst(const cg_game *g);
 int game_precision(const cg_game *g);
 hipStream_t game_stream(const cg_game *g);
 // Records an error message for cg_last_error(); returns code.

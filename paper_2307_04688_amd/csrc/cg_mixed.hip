@@ -28,7 +28,7 @@ namespace cg {
 // G[i] = V_i transformed (DCT-I) along mode i only.
 __global__ __launch_bounds__(256) void k_taylor_a(const Inst *__restrict__ tab, int bpi)
 {
-    const Inst &I = tab[blockIdx.x / bpi];
+    const InstView I = inst_view(tab, blockIdx.x / bpi);
     const int blk = blockIdx.x % bpi;
     const GameConst *__restrict__ gc = I.gc;
     const GameStatus *st = I.st;
@@ -58,7 +58,7 @@ __global__ __launch_bounds__(256) void k_taylor_a(const Inst *__restrict__ tab, 
 // jm enumerates the modes other than i in increasing order; col = k_i.
 __global__ __launch_bounds__(256) void k_taylor_b(const Inst *__restrict__ tab, int bpi)
 {
-    const Inst &I = tab[blockIdx.x / bpi];
+    const InstView I = inst_view(tab, blockIdx.x / bpi);
     const int blk = blockIdx.x % bpi;
     const GameConst *__restrict__ gc = I.gc;
     const GameStatus *st = I.st;
@@ -148,7 +148,7 @@ template <int D, int N4, int NC, int RB>
 __global__ __launch_bounds__(256) void k_contract_corr(const Inst *__restrict__ tab, int bpi,
                                                        int blocks_per_player)
 {
-    const Inst &I = tab[blockIdx.x / bpi];
+    const InstView I = inst_view(tab, blockIdx.x / bpi);
     const int blk = blockIdx.x % bpi;
     const GameConst *__restrict__ gc = I.gc;
     const GameStatus *st = I.st;

@@ -445,7 +445,7 @@ hipError_t infer_game(const GameConst &hc, const float *P, const float *theta, d
 {
     Theta th;
     for (int c = 0; c < 6; ++c) th.t[c] = theta[c];
-    const Inst &I = game_inst(g);
+    const InstPtrs &I = game_inst(g);
     hipError_t e = hipSuccess;
     for (long long r0 = 0; r0 < hc.NN && e == hipSuccess; r0 += nb) {
         const int cnt = (int)(hc.NN - r0 < nb ? hc.NN - r0 : nb);
@@ -555,7 +555,7 @@ int cg_mlp_features(cg_game *game, const float *theta, double t_scale, float *X,
     if (hc.d != 3) return set_error(CG_EUNSUPPORTED, "the warm-start network is for d = 3 games");
     Theta th;
     for (int c = 0; c < 6; ++c) th.t[c] = theta[c];
-    const Inst &I = game_inst(game);
+    const InstPtrs &I = game_inst(game);
     hipStream_t s = game_stream(game);
     hipLaunchKernelGGL(k_features, dim3((unsigned)((hc.NN + 255) / 256)), dim3(256), 0, s, I.gc, I.st, I.V, th,
                        t_scale, 0LL, (int)hc.NN, X, T);

@@ -35,7 +35,7 @@ namespace cg {
 template <int D, int N4, int NC, int RB>
 __global__ __launch_bounds__(256) void k_contract_f64(const Inst *__restrict__ tab, int bpi, int blocks_per_player)
 {
-    const Inst &I = tab[blockIdx.x / bpi];
+    const InstView I = inst_view(tab, blockIdx.x / bpi);
     const int blk = blockIdx.x % bpi;
     const GameConst *__restrict__ gc = I.gc;
     const GameStatus *st = I.st;
@@ -227,7 +227,7 @@ __device__ void finish_step(const GameConst *__restrict__ gc, GameStatus *st, in
 template <int D, int N4, int NC, bool COMPOSE>
 __global__ __launch_bounds__(256) void k_line_f64(const Inst *__restrict__ tab, int bpi, int blocks_per_player)
 {
-    const Inst &I = tab[blockIdx.x / bpi];
+    const InstView I = inst_view(tab, blockIdx.x / bpi);
     const int blk = blockIdx.x % bpi;
     const GameConst *__restrict__ gc = I.gc;
     GameStatus *st = I.st;

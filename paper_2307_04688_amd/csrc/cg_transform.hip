@@ -96,7 +96,7 @@ __device__ __forceinline__ long long packed_index(const GameConst *__restrict__ 
 
 __global__ __launch_bounds__(256) void k_tf_fast(const Inst *__restrict__ tab, int bpi, int mixed)
 {
-    const Inst &I = tab[blockIdx.x / bpi];
+    const InstView I = inst_view(tab, blockIdx.x / bpi);
     const int blk = blockIdx.x % bpi;
     const GameConst *__restrict__ gc = I.gc;
     const GameStatus *st = I.st;
@@ -173,7 +173,7 @@ __global__ __launch_bounds__(256) void k_tf_fast(const Inst *__restrict__ tab, i
 // q over Q consecutive inner positions (the two fast modes flattened).
 __global__ __launch_bounds__(256) void k_tf_outer(const Inst *__restrict__ tab, int bpi, int mixed, int Q)
 {
-    const Inst &I = tab[blockIdx.x / bpi];
+    const InstView I = inst_view(tab, blockIdx.x / bpi);
     const int blk = blockIdx.x % bpi;
     const GameConst *__restrict__ gc = I.gc;
     const GameStatus *st = I.st;
