@@ -169,7 +169,7 @@ def run_batch(cg, W, torch, steps: int, warmup: int, count: int = 256, time_step
             "fp64_one_at_a_time_solves_per_s": int(ok_s.sum()) / t_single,
             "speedup_vs_fp64_one_at_a_time": (int(ok_b.sum()) / t_batch) / (int(ok_s.sum()) / t_single),
             "diverged_batch": int((~ok_b).sum()), "diverged_fp64_one_at_a_time": int((~ok_s).sum()),
-            "groups": groups, "rb_per_group": rb, "autotune_s": t_tune,
+            "groups": groups, "tiles_per_group (rows blocks of 16 per wave, outer values per slab)": rb, "autotune_s": t_tune,
             "max_rel_V_vs_fp64": worst, "max_rms_rel_V_vs_fp64": worst_rms,
             "err_instances": int((ok_b & ok_s).sum()), "median_rel_V_vs_fp64": float(np.median(errs)),
             "instances_rel_V_above_1e-8": int(np.sum(np.array(errs) > 1e-8))}

@@ -173,9 +173,10 @@ int cg_set_state(cg_game *game, const double *V_dev, const double *U_dev);
  * array, copied) must stay valid and must not be used on other streams while
  * the batch works; ws_dev (>= cg_batch_workspace_bytes(count), 256-byte
  * aligned, device) holds the device tables; work is queued on 'stream'.
- * cg_batch_autotune: for every group, times the contraction's row blocking
- * (16, 32 or 64 nodes per wave) over 'trial_steps' iterations and keeps the
- * fastest; it resets every game of the batch to V = 0, u = A.  Synchronises.
+ * cg_batch_autotune: for every group, times the contraction's tile shapes
+ * (16, 32 or 64 nodes per wave; one or two values of the outer modes per
+ * coefficient slab) over 'trial_steps' iterations and keeps the fastest; it
+ * resets every game of the batch to V = 0, u = A.  Synchronises.
  * cg_batch_solve: like cg_solve for every game at once; steps_done and
  * residuals (host arrays of count entries, nullable) receive each game's
  * iteration count and last residual.  Synchronises.  Returns
@@ -183,8 +184,9 @@ int cg_set_state(cg_game *game, const double *V_dev, const double *U_dev);
  * if some game produced a non-finite value: that game stopped at that
  * iteration, its residuals entry is non-finite, and every other game ran on
  * unaffected (its entries are valid).
- * cg_batch_groups: number of groups and, if rb is not NULL, the row blocking
- * chosen per group (host array of CG_MAX_GROUPS entries). */
+ * cg_batch_groups: number of groups and, for arrays that are not NULL (host,
+ * CG_MAX_GROUPS entries each), the row blocks of 16 per wave (rb) and the
+ * outer values per coefficient slab (ocb) chosen per group. */
 #define CG_MAX_GROUPS 64
 typedef struct cg_batch cg_batch;
 size_t cg_batch_workspace_bytes(int32_t count);
@@ -192,7 +194,7 @@ int cg_batch_create(cg_game *const *games, int32_t count, void *ws_dev, size_t w
                     cg_batch **out);
 int cg_batch_autotune(cg_batch *batch, int32_t trial_steps);
 int cg_batch_solve(cg_batch *batch, int32_t max_steps, double tol, int32_t *steps_done, double *residuals);
-int cg_batch_groups(cg_batch *batch, int32_t *rb);
+int cg_batch_groups(cg_batch *batch, int32_t *rb, int32_t *ocb);
 int cg_batch_destroy(cg_batch *batch);
 
 /* Learned warm start (an addition to the method: Section 2.2 leaves the
@@ -271,6 +273,14 @@ int cg_solve_warm(cg_game *game, const float *params, const float *theta, double
  * previous cg_profile call; the record is then cleared.  Costs one event
  * pair per step while enabled. */
 int cg_profile(cg_game *game, int enable, double *kernel_ms, int64_t *launches);
+
+/* Tile shapes of the game's contraction kernel: rb row blocks of 16 nodes per
+ * wave (1, 2 or 4) and ocb values of the outer modes per coefficient slab
+ * (1 or 2; 1 when d = 2).  Defaults: rb = 2 (CG_FP32_CORR: 1), ocb = 2 (d = 2:
+ * 1).  Results do not depend on
+ * rb; ocb changes where the binary32 partial sums of CG_FP32_CORR enter
+ * FP64.  CG_EINVAL for other values. */
+int cg_set_tiles(cg_game *game, int32_t rb, int32_t ocb);
 
 #ifdef __cplusplus
 }

@@ -69,12 +69,13 @@ def lib() -> C.CDLL:
     L.cg_get_state.argtypes = [vp, vp, vp, ip]
     L.cg_set_state.argtypes = [vp, vp, vp]
     L.cg_profile.argtypes = [vp, C.c_int, dp, C.POINTER(C.c_int64)]
+    L.cg_set_tiles.argtypes = [vp, C.c_int32, C.c_int32]
     L.cg_batch_workspace_bytes.restype = C.c_size_t
     L.cg_batch_workspace_bytes.argtypes = [C.c_int32]
     L.cg_batch_create.argtypes = [C.POINTER(vp), C.c_int32, vp, C.c_size_t, vp, C.POINTER(vp)]
     L.cg_batch_autotune.argtypes = [vp, C.c_int32]
     L.cg_batch_solve.argtypes = [vp, C.c_int32, C.c_double, ip, dp]
-    L.cg_batch_groups.argtypes = [vp, ip]
+    L.cg_batch_groups.argtypes = [vp, ip, ip]
     L.cg_batch_destroy.argtypes = [vp]
     fp = C.POINTER(C.c_float)
     L.cg_mlp_param_count.restype = C.c_int64
@@ -189,6 +190,10 @@ class ChebGame:
         _check(lib().cg_profile(self.handle, 1 if enable else 0, C.byref(ms), C.byref(n)))
         return ms.value, n.value
 
+    def set_tiles(self, rb: int = 2, ocb: int = 1):
+        """Contraction tile shapes: row blocks of 16 per wave, outer values per slab."""
+        _check(lib().cg_set_tiles(self.handle, rb, ocb))
+
     def reset(self):
         """Back to the zero terminal value V = 0, u = A (iteration count kept)."""
         import torch
@@ -231,14 +236,16 @@ class ChebBatch:
         self.handle = h
 
     def autotune(self, trial_steps: int = 3):
-        """Pick the contraction row blocking per group; resets every game to V=0, u=A."""
+        """Pick the contraction tile shapes per group; resets every game to V=0, u=A."""
         _check(lib().cg_batch_autotune(self.handle, trial_steps))
         return self.groups()
 
     def groups(self) -> list:
+        """[(rows blocks of 16 per wave, outer values per slab)] per group."""
         rb = (C.c_int32 * 64)()
-        n = _check(lib().cg_batch_groups(self.handle, rb))
-        return list(rb[:n])
+        ocb = (C.c_int32 * 64)()
+        n = _check(lib().cg_batch_groups(self.handle, rb, ocb))
+        return list(zip(rb[:n], ocb[:n]))
 
     def solve(self, max_steps: int, tol: float = 0.0):
         """Returns (status, steps_done[count], last residual[count]).  A game

@@ -186,6 +186,12 @@ struct cg_game {
 };
 
 namespace cg {
+void default_tiles(int d, int precision, int &rb, int &ocb)
+{
+    // measured on the d = 3, N = 32 game: FP64 fastest at (2, 2), FP32_CORR at (1, 2)
+    rb = precision == CG_FP32_CORR ? 1 : 2;
+    ocb = d >= 3 ? 2 : 1;
+}
 const GameConst &game_consts(const cg_game *g) { return g->hc; }
 const InstPtrs &game_inst(const cg_game *g) { return g->inst; }
 Inst inst_offsets(const InstPtrs &p, const void *table_dev)
@@ -404,7 +410,7 @@ int cg_init_game(const cg_game_desc *g, int precision, void *ws_dev, size_t ws_b
     b.ev_begin = b.ev_end = nullptr;
     b.tab = (const Inst *)(G->ws + L.tab);
     b.count = 1;
-    b.rb = 2;
+    default_tiles(hc.d, precision, b.rb, b.ocb);
     InstPtrs &hi = G->inst;
     hi.gc = b.gc;
     hi.st = b.status;
@@ -576,6 +582,16 @@ int cg_get_state(cg_game *g, double *V_dev, double *U_dev, int32_t *r)
         if (rc != CG_OK) return rc;
         *r = st.total_steps;
     }
+    return CG_OK;
+}
+
+int cg_set_tiles(cg_game *g, int32_t rb, int32_t ocb)
+{
+    if (!g) return fail(CG_EINVAL, "game is NULL");
+    if (!(rb == 1 || rb == 2 || rb == 4)) return fail(CG_EINVAL, "rb must be 1, 2 or 4");
+    if (!(ocb == 1 || (ocb == 2 && g->hc.d >= 3))) return fail(CG_EINVAL, "ocb must be 1 (or 2 when d >= 3)");
+    g->b.rb = rb;
+    g->b.ocb = ocb;
     return CG_OK;
 }
 

@@ -20,6 +20,7 @@ struct Group {
     std::vector<int> members;  // indices into the batch's game list
     size_t tab_off;            // byte offset of the group's table in the workspace
     int rb;                    // row blocks of 16 per wave in the contraction
+    int ocb;                   // outer-mode values per LDS slab in the contraction
 };
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -123,6 +124,7 @@ StepBuffers group_buffers(cg_batch *B, const Group &G)
     b.tab = (const Inst *)(B->ws + G.tab_off);
     b.count = (int)G.members.size();
     b.rb = G.rb;
+    b.ocb = G.ocb;
     return b;
 }
 
@@ -220,7 +222,7 @@ int cg_batch_create(cg_game *const *games, int32_t count, void *ws_dev, size_t w
             Group G;
             G.hc = hc;
             G.precision = prec;
-            G.rb = 2;
+            default_tiles(hc.d, prec, G.rb, G.ocb);
             G.tab_off = 0;
             B->groups.push_back(G);
             found = &B->groups.back();
@@ -281,11 +283,13 @@ int cg_batch_autotune(cg_batch *B, int32_t trial_steps)
     int rc = CG_OK;
     hipLaunchKernelGGL(k_batch_arm, dim3((n + 127) / 128), dim3(128), 0, B->stream, all, n, 0.0, 1);
     for (Group &G : B->groups) {
-        const int cands[3] = {1, 2, 4};
+        const int cands[6][2] = {{1, 1}, {2, 1}, {4, 1}, {1, 2}, {2, 2}, {4, 2}};
         float best = 1e30f;
-        int best_rb = G.rb;
-        for (int rb : cands) {
-            G.rb = rb;
+        int best_rb = G.rb, best_ocb = G.ocb;
+        for (const auto &cnd : cands) {
+            if (cnd[1] == 2 && G.hc.d < 3) continue;  // one outer value when d = 2
+            G.rb = cnd[0];
+            G.ocb = cnd[1];
             StepBuffers b = group_buffers(B, G);
             hipError_t e = launch_step(G.hc, b, B->stream);  // warm-up
             if (e == hipSuccess) e = hipEventRecord(e0, B->stream);
@@ -300,10 +304,12 @@ int cg_batch_autotune(cg_batch *B, int32_t trial_steps)
             }
             if (ms < best) {
                 best = ms;
-                best_rb = rb;
+                best_rb = G.rb;
+                best_ocb = G.ocb;
             }
         }
         G.rb = best_rb;
+        G.ocb = best_ocb;
         if (rc != CG_OK) break;
     }
     (void)hipEventDestroy(e0);
@@ -363,11 +369,13 @@ int cg_batch_solve(cg_batch *B, int32_t max_steps, double tol, int32_t *steps_do
     return CG_OK;
 }
 
-int cg_batch_groups(cg_batch *B, int32_t *rb)
+int cg_batch_groups(cg_batch *B, int32_t *rb, int32_t *ocb)
 {
     if (!B) return set_error(CG_EINVAL, "batch is NULL");
-    if (rb)
-        for (size_t i = 0; i < B->groups.size(); ++i) rb[i] = B->groups[i].rb;
+    for (size_t i = 0; i < B->groups.size(); ++i) {
+        if (rb) rb[i] = B->groups[i].rb;
+        if (ocb) ocb[i] = B->groups[i].ocb;
+    }
     return (int)B->groups.size();
 }
 

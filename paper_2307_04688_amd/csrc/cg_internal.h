@@ -125,6 +125,7 @@ struct StepBuffers {
     const Inst *tab;              // device table of the instances of this launch
     int count;                    // instances in the table (same d, N, precision)
     int rb;                       // rows blocks of 16 per wave in the contraction (1, 2 or 4)
+    int ocb;                      // outer-mode values per LDS slab in the contraction (1 or 2)
 };
 hipError_t launch_transform_game(const GameConst &hc, const StepBuffers &b, hipStream_t s);
 hipError_t launch_step(const GameConst &hc, const StepBuffers &b, hipStream_t s);
@@ -140,6 +141,8 @@ const GameConst &game_consts(const cg_game *g);
 const InstPtrs &game_inst(const cg_game *g);
 int game_precision(const cg_game *g);
 hipStream_t game_stream(const cg_game *g);
+// Default contraction tile shapes (row blocks per wave, outer values per slab).
+void default_tiles(int d, int precision, int &rb, int &ocb);
 // Records an error message for cg_last_error(); returns code.
 int set_error(int code, const char *msg);
 

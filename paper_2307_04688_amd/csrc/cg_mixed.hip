@@ -11,7 +11,8 @@
 // E0 and E1 are small FP64 mode products of V (no point evaluation), computed
 // once per iteration; only the second-order remainder R, of relative size
 // ~Delta^2, runs on binary32 MFMA (inputs rounded to binary32, products
-// accumulated in binary32 over N4 K-rows, then added into FP64).
+// accumulated in binary32 over the K-rows of one LDS slab -- N4 or 2 N4 --
+// then added into FP64).
 //
 // A2 is built per K element from per-mode quantities: with T = T_k(x),
 // Tb = T_k(xbar), P = T_k'(xbar) Delta (first-order increment) and
@@ -144,7 +145,45 @@ struct ModeRec {
     }
 };
 
-template <int D, int N4, int NC, int RB>
+// The same quantities for k = k0, k0 + 4, k0 + 8, ... (k0 in 0..3), by the
+// stride-4 recurrences T_{k+4} = 2 T_4 T_k - T_{k-4} (from T_m T_n =
+// (T_{m+n} + T_{|m-n|}) / 2) and its derivative, started from T_{k0} and
+// T_{k0-4} = T_{4-k0}: a lane that needs every fourth k steps N/4 times.
+struct ModeRec4 {
+    double dl, t4, b4, p4;
+    double t0, t1, b0, b1, p0, p1;  // k - 4 and k: at x, at xbar, derivative at xbar
+    __device__ void init(double x, double xb, int k0)
+    {
+        dl = x - xb;
+        double T[5], B[5], P[5];
+        T[0] = 1.0; T[1] = x; B[0] = 1.0; B[1] = xb; P[0] = 0.0; P[1] = 1.0;
+#pragma unroll
+        for (int k = 1; k < 4; ++k) {
+            T[k + 1] = 2.0 * x * T[k] - T[k - 1];
+            B[k + 1] = 2.0 * xb * B[k] - B[k - 1];
+            P[k + 1] = 2.0 * B[k] + 2.0 * xb * P[k] - P[k - 1];
+        }
+        t4 = T[4]; b4 = B[4]; p4 = P[4];
+        // select without indexing the arrays by a lane-dependent value
+        t1 = T[0]; b1 = B[0]; p1 = P[0]; t0 = T[4]; b0 = B[4]; p0 = P[4];
+#pragma unroll
+        for (int m = 1; m < 4; ++m)
+            if (k0 == m) { t1 = T[m]; b1 = B[m]; p1 = P[m]; t0 = T[4 - m]; b0 = B[4 - m]; p0 = P[4 - m]; }
+    }
+    __device__ void get(double &T, double &Tb, double &P, double &R1) const
+    {
+        T = t1; Tb = b1; P = p1 * dl; R1 = (t1 - b1) - P;
+    }
+    __device__ void advance4()
+    {
+        const double tn = 2.0 * t4 * t1 - t0;
+        const double bn = 2.0 * b4 * b1 - b0;
+        const double pn = 2.0 * p4 * b1 + 2.0 * b4 * p1 - p0;
+        t0 = t1; t1 = tn; b0 = b1; b1 = bn; p0 = p1; p1 = pn;
+    }
+};
+
+template <int D, int N4, int NC, int RB, int OCB>
 __global__ __launch_bounds__(256) void k_contract_corr(const Inst *__restrict__ tab, int bpi,
                                                        int blocks_per_player)
 {
@@ -160,8 +199,9 @@ __global__ __launch_bounds__(256) void k_contract_corr(const Inst *__restrict__ 
     constexpr int ROWS_W = RB * 16;
     constexpr int ROWS_B = 4 * ROWS_W;
     constexpr int LDB = NC == 32 ? 48 : 16;     // slab rows (floats): kq groups on disjoint banks
-    constexpr int SLAB = N4 * LDB;
-    constexpr int SLAB_E4 = N4 * NC / 4;        // float4 elements per slab
+    constexpr int SLAB = OCB * N4 * LDB;        // OCB outer values per slab
+    constexpr int OC_E4 = N4 * NC / 4;          // float4 elements per outer value
+    constexpr int SLAB_E4 = OCB * OC_E4;
     constexpr int PF = (SLAB_E4 + 255) / 256;
     __shared__ float lds[2 * SLAB];
     __shared__ double dls[ROWS_B * (D - 1)];    // Delta of every row, for the epilogue
@@ -185,6 +225,7 @@ __global__ __launch_bounds__(256) void k_contract_corr(const Inst *__restrict__ 
     // ---- per row: node, shift, inner-mode quantities, outer-mode recurrences ----
     float Tc[RB][N4 / 4], Rc[RB][N4 / 4], Pc[RB][N4 / 4];
     ModeRec ra[RB], rb_[RB];
+    ModeRec4 ra4[RB];  // d = 3: the outer mode, this lane's values oc = 4 w + kq
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb) {
         const int j = min(row0 + rb * 16 + r16, NN - 1);
@@ -207,20 +248,19 @@ __global__ __launch_bounds__(256) void k_contract_corr(const Inst *__restrict__ 
             xb[t] = xbar;
             if (kq == 0) dls[(wave * ROWS_W + rb * 16 + r16) * (D - 1) + t] = xs[t] - xbar;
         }
-        ModeRec rc;
-        rc.init(xs[D - 2], xb[D - 2]);
+        ModeRec4 rc;  // this lane's k = 4 t + kq
+        rc.init(xs[D - 2], xb[D - 2], kq);
 #pragma unroll
-        for (int k = 0; k < N4; ++k) {
-            if ((k & 3) == kq) {
-                double T, Tb, P, R1;
-                rc.get(T, Tb, P, R1);
-                Tc[rb][k >> 2] = (float)T;
-                Rc[rb][k >> 2] = (float)R1;
-                Pc[rb][k >> 2] = (float)P;
-            }
-            rc.advance(k);
+        for (int t = 0; t < N4 / 4; ++t) {
+            double T, Tb, P, R1;
+            rc.get(T, Tb, P, R1);
+            Tc[rb][t] = (float)T;
+            Rc[rb][t] = (float)R1;
+            Pc[rb][t] = (float)P;
+            rc.advance4();
         }
-        if (D >= 3) ra[rb].init(xs[0], xb[0]);
+        if (D == 3) ra4[rb].init(xs[0], xb[0], kq);
+        if (D >= 4) ra[rb].init(xs[0], xb[0]);
         if (D >= 4) rb_[rb].init(xs[1], xb[1]);
     }
 
@@ -236,12 +276,15 @@ __global__ __launch_bounds__(256) void k_contract_corr(const Inst *__restrict__ 
         }
 
     const float4 *Bg = reinterpret_cast<const float4 *>(Bp32 + (long long)player * gc->K * NC);
+    const int n_outer = (D == 2) ? 1 : (D == 3 ? N : N * N);
     float4 pf[PF];
-    auto load_slab = [&](int oc) {
+    auto load_slab = [&](int sb) {  // outer values past the last one read as zero
 #pragma unroll
         for (int q = 0; q < PF; ++q) {
             const int e4 = tid + q * 256;
-            if (e4 < SLAB_E4) pf[q] = Bg[(long long)oc * SLAB_E4 + e4];
+            if (e4 < SLAB_E4)
+                pf[q] = sb * OCB + e4 / OC_E4 < n_outer ? Bg[(long long)sb * SLAB_E4 + e4]
+                                                       : make_float4(0.f, 0.f, 0.f, 0.f);
         }
     };
     auto store_slab = [&](float *buf) {
@@ -256,19 +299,45 @@ __global__ __launch_bounds__(256) void k_contract_corr(const Inst *__restrict__ 
         }
     };
 
-    const int n_outer = (D == 2) ? 1 : (D == 3 ? N : N * N);
+    float myRem[RB], myLin[RB], myFO[RB];
+    const int n_slabs = (n_outer + OCB - 1) / OCB;
     load_slab(0);
     store_slab(lds);
     __syncthreads();
-    for (int oc = 0; oc < n_outer; ++oc) {
-        const float *cb = lds + (oc & 1) * SLAB;
-        const bool more = oc + 1 < n_outer;
-        if (more) load_slab(oc + 1);
+    for (int sb = 0; sb < n_slabs; ++sb) {
+        const bool more = sb + 1 < n_slabs;
+        if (more) load_slab(sb + 1);
+#pragma unroll
+        for (int ocl = 0; ocl < OCB; ++ocl) {
+        const int oc = sb * OCB + ocl;
+        const float *cb = lds + (sb & 1) * SLAB + ocl * N4 * LDB;
         // outer-mode factors of the remainder recursion
         float fRem[RB], fLin[RB], fFO[RB];
+        if (D == 3) {
+            // the lane with kq = oc mod 4 holds them (computed once per four outer values)
+            if ((oc & 3) == 0) {
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb) {
+                    if (oc > 0) ra4[rb].advance4();
+                    double Ta, Tba, Pa, R1a;
+                    ra4[rb].get(Ta, Tba, Pa, R1a);
+                    myRem[rb] = (float)R1a;
+                    myLin[rb] = (float)(Tba + Pa);
+                    myFO[rb] = (float)Pa;
+                }
+            }
+            const int src = r16 + 16 * (oc & 3);
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) {
+                fRem[rb] = __shfl(myRem[rb], src);
+                fLin[rb] = __shfl(myLin[rb], src);
+                fFO[rb] = __shfl(myFO[rb], src);
+            }
+        }
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
-            if (D == 2) {
+            if (D == 3) {
+            } else if (D == 2) {
                 fRem[rb] = 0.f; fLin[rb] = 1.f; fFO[rb] = 0.f;
             } else {
                 double Ta, Tba, Pa, R1a;
@@ -287,7 +356,7 @@ __global__ __launch_bounds__(256) void k_contract_corr(const Inst *__restrict__ 
                 fFO[rb] = (float)FO;
             }
         }
-        // all B fragments of the slab first, so the LDS latency is paid once
+        // all B fragments of this outer value first, so the LDS latency is paid once
         float bf[N4 / 4][NCB];
 #pragma unroll
         for (int t = 0; t < N4 / 4; ++t)
@@ -303,20 +372,8 @@ __global__ __launch_bounds__(256) void k_contract_corr(const Inst *__restrict__ 
                     acc[rb][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bf[t][c], acc[rb][c], 0, 0, 0);
             }
         }
-        // binary32 partial sums of this slab into FP64
-#pragma unroll
-        for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-            for (int c = 0; c < NCB; ++c) {
-#pragma unroll
-                for (int v = 0; v < 4; ++v) acc64[rb][c][v] += (double)acc[rb][c][v];
-                acc[rb][c] = f32x4{0.f, 0.f, 0.f, 0.f};
-            }
-        // advance the outer-mode recurrences
-        if (D == 3) {
-#pragma unroll
-            for (int rb = 0; rb < RB; ++rb) ra[rb].advance(oc);
-        } else if (D == 4) {
+        // advance the outer-mode recurrences (d = 3: at the next window)
+        if (D == 4) {
             const int kb = oc % N;
             if (kb == N - 1) {
                 const int ka = oc / N;
@@ -330,7 +387,17 @@ __global__ __launch_bounds__(256) void k_contract_corr(const Inst *__restrict__ 
                 for (int rb = 0; rb < RB; ++rb) rb_[rb].advance(kb);
             }
         }
-        if (more) store_slab(lds + ((oc + 1) & 1) * SLAB);
+        }
+        // binary32 partial sums of this slab (OCB * N4 K-rows) into FP64
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int c = 0; c < NCB; ++c) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc64[rb][c][v] += (double)acc[rb][c][v];
+                acc[rb][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+            }
+        if (more) store_slab(lds + ((sb + 1) & 1) * SLAB);
         __syncthreads();
     }
 
@@ -369,8 +436,12 @@ static hipError_t launch_corr_dnr(const GameConst &hc, const StepBuffers &b, hip
     const int NN = (int)hc.NN;
     const int bpp = (NN + 4 * RB * 16 - 1) / (4 * RB * 16);
     const int bpi = bpp * D;
-    hipLaunchKernelGGL((k_contract_corr<D, N4, NC, RB>), dim3((unsigned)(bpi * b.count)), dim3(256), 0, s, b.tab, bpi,
-                       bpp);
+    if (D >= 3 && b.ocb == 2)
+        hipLaunchKernelGGL((k_contract_corr<D, N4, NC, RB, D >= 3 ? 2 : 1>), dim3((unsigned)(bpi * b.count)),
+                           dim3(256), 0, s, b.tab, bpi, bpp);
+    else
+        hipLaunchKernelGGL((k_contract_corr<D, N4, NC, RB, 1>), dim3((unsigned)(bpi * b.count)), dim3(256), 0, s,
+                           b.tab, bpi, bpp);
     return hipGetLastError();
 }
 

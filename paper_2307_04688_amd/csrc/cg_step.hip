@@ -29,10 +29,10 @@ namespace cg {
 // interleaved by 4, unlike the f32 forms).
 //
 // The packed operand of the player (K x NC) streams through LDS in slabs of
-// N4 rows (one value of the outer modes), double-buffered: the block loads
-// slab s+1 into registers while its waves run the MFMAs of slab s.  The
+// OCB * N4 rows (OCB values of the outer modes), double-buffered: the block
+// loads slab s+1 into registers while its waves run the MFMAs of slab s.  The
 // result rows go to W[i][j][0..NC) (L2/MALL-resident) for the line kernel.
-template <int D, int N4, int NC, int RB>
+template <int D, int N4, int NC, int RB, int OCB>
 __global__ __launch_bounds__(256) void k_contract_f64(const Inst *__restrict__ tab, int bpi, int blocks_per_player)
 {
     const InstView I = inst_view(tab, blockIdx.x / bpi);
@@ -46,8 +46,9 @@ __global__ __launch_bounds__(256) void k_contract_f64(const Inst *__restrict__ t
     constexpr int ROWS_W = RB * 16;
     constexpr int ROWS_B = 4 * ROWS_W;
     constexpr int LDB = NC == 32 ? 48 : 16;       // slab rows: kq groups on disjoint banks
-    constexpr int SLAB = N4 * LDB;
-    constexpr int SLAB_E2 = N4 * NC / 2;          // double2 elements per slab
+    constexpr int SLAB = OCB * N4 * LDB;
+    constexpr int OC_E2 = N4 * NC / 2;            // double2 elements per outer value
+    constexpr int SLAB_E2 = OCB * OC_E2;          // double2 elements per slab
     constexpr int PF = (SLAB_E2 + 255) / 256;     // double2 prefetch registers per thread
     __shared__ double lds[2 * SLAB];
 
@@ -102,12 +103,14 @@ __global__ __launch_bounds__(256) void k_contract_f64(const Inst *__restrict__ t
         for (int c = 0; c < NCB; ++c) acc[rb][c] = f64x4{0.0, 0.0, 0.0, 0.0};
 
     const double2 *Bg = reinterpret_cast<const double2 *>(Bp + (long long)player * gc->K * NC);
+    const int n_outer = (D == 2) ? 1 : (D == 3 ? N : N * N);
     double2 pf[PF];
-    auto load_slab = [&](int oc) {
+    auto load_slab = [&](int sb) {  // outer values past the last one read as zero
 #pragma unroll
         for (int q = 0; q < PF; ++q) {
             const int e2 = tid + q * 256;
-            if (e2 < SLAB_E2) pf[q] = Bg[(long long)oc * SLAB_E2 + e2];
+            if (e2 < SLAB_E2)
+                pf[q] = sb * OCB + e2 / OC_E2 < n_outer ? Bg[(long long)sb * SLAB_E2 + e2] : double2{0.0, 0.0};
         }
     };
     auto store_slab = [&](double *buf) {
@@ -125,14 +128,17 @@ __global__ __launch_bounds__(256) void k_contract_f64(const Inst *__restrict__ t
     double Ta_prev[RB], Ta[RB], Tb_prev[RB], Tb[RB];
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb) { Ta_prev[rb] = 0.0; Ta[rb] = 1.0; Tb_prev[rb] = 0.0; Tb[rb] = 1.0; }
-    const int n_outer = (D == 2) ? 1 : (D == 3 ? N : N * N);
+    const int n_slabs = (n_outer + OCB - 1) / OCB;
     load_slab(0);
     store_slab(lds);
     __syncthreads();
-    for (int oc = 0; oc < n_outer; ++oc) {
-        const double *cb = lds + (oc & 1) * SLAB;
-        const bool more = oc + 1 < n_outer;
-        if (more) load_slab(oc + 1);
+    for (int sb = 0; sb < n_slabs; ++sb) {
+        const bool more = sb + 1 < n_slabs;
+        if (more) load_slab(sb + 1);
+#pragma unroll
+        for (int ocl = 0; ocl < OCB; ++ocl) {
+        const int oc = sb * OCB + ocl;
+        const double *cb = lds + (sb & 1) * SLAB + ocl * N4 * LDB;
         double F[RB];
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) F[rb] = (D == 2) ? 1.0 : (D == 3 ? Ta[rb] : Ta[rb] * Tb[rb]);
@@ -179,7 +185,8 @@ __global__ __launch_bounds__(256) void k_contract_f64(const Inst *__restrict__ t
                 }
             }
         }
-        if (more) store_slab(lds + ((oc + 1) & 1) * SLAB);
+        }
+        if (more) store_slab(lds + ((sb + 1) & 1) * SLAB);
         __syncthreads();
     }
 
@@ -320,8 +327,12 @@ static hipError_t launch_contract_dnr(const GameConst &hc, const StepBuffers &b,
     const int NN = (int)hc.NN;
     const int bpp = (NN + 4 * RB * 16 - 1) / (4 * RB * 16);
     const int bpi = bpp * D;
-    hipLaunchKernelGGL((k_contract_f64<D, N4, NC, RB>), dim3((unsigned)(bpi * b.count)), dim3(256), 0, s, b.tab, bpi,
-                       bpp);
+    if (D >= 3 && b.ocb == 2)
+        hipLaunchKernelGGL((k_contract_f64<D, N4, NC, RB, D >= 3 ? 2 : 1>), dim3((unsigned)(bpi * b.count)), dim3(256),
+                           0, s, b.tab, bpi, bpp);
+    else
+        hipLaunchKernelGGL((k_contract_f64<D, N4, NC, RB, 1>), dim3((unsigned)(bpi * b.count)), dim3(256), 0, s,
+                           b.tab, bpi, bpp);
     return hipGetLastError();
 }
 

@@ -103,8 +103,8 @@ def test_batch_autotune_and_reset(cg):
     games = ragged(6, seed=15)
     handles = [cg.ChebGame(g, cg.FP32_CORR) for g in games]
     B = cg.ChebBatch(handles)
-    rb = B.autotune(2)
-    assert len(rb) == B.groups().__len__() and all(r in (1, 2, 4) for r in rb)
+    tiles = B.autotune(2)
+    assert len(tiles) == len(B.groups()) and all(r in (1, 2, 4) and o in (1, 2) for r, o in tiles)
     rc, steps, _ = B.solve(12)
     assert np.all(steps == 12)
     for g, h in zip(games, handles):

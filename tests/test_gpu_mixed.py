@@ -85,14 +85,15 @@ def test_one_step_within_a_priori_bound(cg, orc):
     steps) against the oracle's step, per sampled (player, node), within
 
         |dV| <= delta * sum_{k_i} max_line |T_{k_i}| * |dw_{k_i}|,
-        |dw_{k_i}| <= (8 u + gamma_{N4}(u)) * sum_K S_K |c[K, k_i]|   (u = 2^-24),
+        |dw_{k_i}| <= (8 u + gamma_{2 N4}(u)) * sum_K S_K |c[K, k_i]|   (u = 2^-24),
         S = |R1_a T_c| + |(Tb_a + P_a) R1_c| + |P_a P_c|,
 
     where A2 = R1_a T_c + (Tb_a + P_a) R1_c + P_a P_c is the second-order
     remainder of the Khatri-Rao basis at the shifted point, the only part
     contracted in binary32: six binary32 factors and c each rounded once, three
     rounded operations to form an element (the terms may cancel, hence S),
-    products accumulated over N4 K-rows in binary32 and then in FP64.  A2 and
+    products accumulated in binary32 over the K-rows of one coefficient slab
+    (up to 2 N4) and then in FP64.  A2 and
     the coefficients come from numpy and the oracle.  The FP64 rest of the
     step adds its own budget, 1e-13 max|V|."""
     g = W.make_game(3, 12, seed=9, per_player=True)
@@ -109,7 +110,8 @@ def test_one_step_within_a_priori_bound(cg, orc):
     delta = 1 - g.rho * g.h
     u32 = 2.0 ** -24
     N4 = (N + 3) // 4 * 4
-    factor = 8 * u32 + N4 * u32 / (1 - N4 * u32)
+    KS = 2 * N4                       # K-rows summed in binary32 per slab
+    factor = 8 * u32 + KS * u32 / (1 - KS * u32)
     idx = np.arange(48, dtype=np.uint64)
     players = (W.uniform(9, 3, idx) * d).astype(int)
     nodes = (W.uniform(9, 4, idx) * N ** d).astype(int)
