@@ -71,6 +71,8 @@ def lib() -> C.CDLL:
         L.or_series.restype = C.c_double
         L.or_argmax_line.argtypes = [C.c_int, _dp, _dp, _ip]
         L.or_argmax_line.restype = C.c_double
+        L.or_simulate.argtypes = [C.POINTER(_Game), _dp, _dp, C.c_int, _dp, _dp]
+        L.or_simulate.restype = None
         L.or_step.argtypes = [C.POINTER(_Game), _dp, _dp, _dp, _dp, _lp]
         L.or_step.restype = C.c_double
         L.or_step_sample.argtypes = [C.POINTER(_Game), _dp, _dp, C.c_long, _ip, _lp, _dp, _dp]
@@ -210,3 +212,14 @@ def solve(g, steps: int, tol: float = 0.0, V=None, U=None):
     G = _game(g)
     n = lib().or_solve(C.byref(G), _d(V), _d(U), steps, tol, _d(res))
     return V, U, res[:n]
+
+
+def simulate(g, U, p0, steps: int):
+    """Equilibrium path from p0 under the interpolated controls U (d, N^d):
+    returns (paths (steps+1, d), controls (steps, d))."""
+    U = _f64(U)
+    p0 = _f64(p0).ravel()
+    paths = np.empty((steps + 1, g.d))
+    ctrl = np.empty((max(steps, 1), g.d))
+    lib().or_simulate(C.byref(_game(g)), _d(U), _d(p0), steps, _d(paths), _d(ctrl))
+    return paths, ctrl[:steps]

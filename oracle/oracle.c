@@ -400,3 +400,40 @@ int or_solve(const or_game *g, double *V, double *U, int steps, double tol, doub
     free(Un);
     return r;
 }
+
+/* Equilibrium time paths (the emission and pollution paths of Section 4):
+ * from p_0, p_{n+1} = p_n + h g(p_n, u*(p_n)), where u*_i(p) is the
+ * Chebyshev interpolant of the nodal controls U_i (Section 3.1) at p, and
+ * the payoff-relevant control is kept in [0, U_M].  Reading: the paper plots
+ * these paths without stating how they are produced; the explicit Euler
+ * step with the scheme's own h and drift is the discrete dynamics the
+ * iteration assumes (Section 2.1), and the interpolant of controls that sit
+ * on the bounds can leave [0, U_M] between nodes, hence the clip.
+ * U has shape (d, N^d); paths (n_steps+1) x d; controls n_steps x d. */
+void or_simulate(const or_game *g, const double *U, const double *p0, int n_steps, double *paths,
+                 double *controls)
+{
+    int d = g->d, Nd[OR_MAXD];
+    for (int l = 0; l < d; ++l) Nd[l] = g->N;
+    long NN = ipow(g->N, d);
+    double *coef = (double *)malloc(sizeof(double) * (size_t)(d * NN));
+    double *work = (double *)malloc(sizeof(double) * (size_t)(NN / g->N > 0 ? NN / g->N : 1));
+    for (int i = 0; i < d; ++i) or_transform(d, Nd, NULL, U + i * NN, coef + i * NN);
+    double p[OR_MAXD], u[OR_MAXD], x[OR_MAXD], b[OR_MAXD];
+    for (int l = 0; l < d; ++l) p[l] = paths[l] = p0[l];
+    for (int n = 0; n < n_steps; ++n) {
+        for (int l = 0; l < d; ++l) x[l] = 2.0 * p[l] / g->pmax - 1.0;
+        for (int i = 0; i < d; ++i) {
+            double v = or_eval_point(d, Nd, coef + i * NN, x, work);
+            u[i] = v < 0.0 ? 0.0 : (v > g->umax ? g->umax : v);
+            if (controls) controls[n * d + i] = u[i];
+        }
+        drift(g, p, u, b);
+        for (int l = 0; l < d; ++l) {
+            p[l] = p[l] + g->h * b[l];
+            paths[(n + 1) * d + l] = p[l];
+        }
+    }
+    free(work);
+    free(coef);
+}
