@@ -318,6 +318,31 @@ def run_eval(cg, W, torch, steps: int, warmup: int, d: int = 4, N: int = 24, npt
     return out
 
 
+def run_sim(cg, W, torch, steps: int, warmup: int, n_paths: int = 1024, n_steps: int = 1000):
+    """Equilibrium paths of the d=3, N=32 game after 200 iterations: n_paths
+    initial states uniform in [0, P_M]^3, n_steps Euler steps under the
+    interpolated controls (one block per path; each step reads every
+    coefficient of the d control tensors once)."""
+    import numpy as np
+    g = W.config_game("C2")
+    G = cg.ChebGame(g, cg.FP64)
+    G.solve(TIME_STEPS)
+    p0 = W.uniform(2, 77, np.arange(n_paths * g.d, dtype=np.uint64)).reshape(n_paths, g.d) * g.p_max
+    for _ in range(warmup):
+        G.simulate(p0, n_steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        paths, ctrl = G.simulate(p0, n_steps)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / max(steps, 1)
+    coef_bytes = g.d * g.N ** g.d * 8
+    return {"workload": f"equilibrium paths, d=3 N=32 after {TIME_STEPS} iterations: {n_paths} paths x {n_steps} steps",
+            "ms": dt * 1e3, "path_steps_per_s": n_paths * n_steps / dt,
+            "coefficient_bytes_read_per_s": n_paths * n_steps * coef_bytes / dt,
+            "final_mean_state": paths[:, -1].mean(dim=0).tolist()}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -326,7 +351,7 @@ def main():
     ap.add_argument("--precision", default="fp32corr", choices=["fp64", "fp32corr"],
                     help="path reported as value; the other is timed beside it")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "batch", "warm", "eval"])
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "batch", "warm", "eval", "sim"])
     ap.add_argument("--cpu-steps", type=int, default=6, help="oracle iterations timed for the CPU baseline")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for scaling rocprof byte counters)")
@@ -345,6 +370,9 @@ def main():
     if args.workload == "batch":
         print("bench: ragged batch of 256 games", file=sys.stderr, flush=True)
         print(json.dumps(run_batch(cg, W, torch, args.steps, args.warmup)), flush=True)
+        return
+    if args.workload == "sim":
+        print(json.dumps(run_sim(cg, W, torch, args.steps, args.warmup)), flush=True)
         return
     if args.workload == "eval":
         print(json.dumps(run_eval(cg, W, torch, args.steps, args.warmup)), flush=True)

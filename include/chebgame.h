@@ -265,6 +265,18 @@ int cg_solve_warm(cg_game *game, const float *params, const float *theta, double
                   double tol, int32_t probe_steps, void *ws, size_t ws_bytes, int32_t batch, int32_t *steps_done,
                   double *residual, int32_t *fell_back);
 
+/* Equilibrium time paths (the emission and pollution paths of Section 4):
+ * for each of n_paths initial states (p0, device, [n_paths][d], physical
+ * units) the state recursion p_{n+1} = p_n + h g(p_n, u*(p_n)) over n_steps,
+ * with u*_i the Chebyshev interpolant (Section 3.1) of the game's current
+ * nodal controls U_i at p, kept in [0, U_M]; points outside [0, P_M]^d use the
+ * polynomial continuation.  paths (device, [n_paths][n_steps+1][d], row 0 =
+ * p0) and controls (device, nullable, [n_paths][n_steps][d]).  Queued on the
+ * game's stream; uses the game's transform buffer, so it must not overlap the
+ * game's iterations (same stream: it does not). */
+int cg_simulate(cg_game *game, const double *p0_dev, int32_t n_paths, int32_t n_steps, double *paths_dev,
+                double *controls_dev);
+
 /* Timing of the contraction kernel (the fused step kernel that carries the
  * mode-n contractions).  With enable != 0, every later step records a pair of
  * HIP events on the game's stream around that kernel's launch.  If kernel_ms

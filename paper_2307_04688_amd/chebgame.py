@@ -70,6 +70,7 @@ def lib() -> C.CDLL:
     L.cg_set_state.argtypes = [vp, vp, vp]
     L.cg_profile.argtypes = [vp, C.c_int, dp, C.POINTER(C.c_int64)]
     L.cg_set_tiles.argtypes = [vp, C.c_int32, C.c_int32]
+    L.cg_simulate.argtypes = [vp, vp, C.c_int32, C.c_int32, vp, vp]
     L.cg_batch_workspace_bytes.restype = C.c_size_t
     L.cg_batch_workspace_bytes.argtypes = [C.c_int32]
     L.cg_batch_create.argtypes = [C.POINTER(vp), C.c_int32, vp, C.c_size_t, vp, C.POINTER(vp)]
@@ -189,6 +190,18 @@ class ChebGame:
         n = C.c_int64()
         _check(lib().cg_profile(self.handle, 1 if enable else 0, C.byref(ms), C.byref(n)))
         return ms.value, n.value
+
+    def simulate(self, p0, steps: int, with_controls: bool = True):
+        """Equilibrium paths from the rows of p0 ([n_paths][d], physical units) under the
+        interpolated controls of the current iterate: (paths [n][steps+1][d], controls [n][steps][d])."""
+        import torch
+        p0 = torch.as_tensor(p0, dtype=torch.float64).to("cuda").contiguous().reshape(-1, self.d)
+        n = p0.shape[0]
+        paths = torch.empty((n, steps + 1, self.d), dtype=torch.float64, device="cuda")
+        ctrl = torch.empty((n, max(steps, 1), self.d), dtype=torch.float64, device="cuda") if with_controls else None
+        _check(lib().cg_simulate(self.handle, _ptr(p0), n, steps, _ptr(paths), _ptr(ctrl)))
+        self._pin_sim = p0
+        return paths, (ctrl[:, :steps] if ctrl is not None else None)
 
     def set_tiles(self, rb: int = 2, ocb: int = 1):
         """Contraction tile shapes: row blocks of 16 per wave, outer values per slab."""
@@ -408,6 +421,10 @@ def set_state(g: ChebGame, V, U=None):
 
 def destroy(g: ChebGame):
     g.destroy()
+
+
+def simulate(g: ChebGame, p0, steps: int, with_controls: bool = True):
+    return g.simulate(p0, steps, with_controls)
 
 
 def batch_create(games: Sequence[ChebGame], stream=None) -> ChebBatch:
