@@ -26,94 +26,89 @@
 
 namespace cg {
 
-// G[i] = V_i transformed (DCT-I) along mode i only.
-__global__ __launch_bounds__(256) void k_taylor_a(const Inst *__restrict__ tab, int bpi)
+// E[i][slot][jm][col] (jm enumerates the modes other than i in increasing
+// order, col = k_i): slot 0 = G_i = V_i transformed (DCT-I) along mode i only,
+// at the nodes of the other modes; slot 1 + s = G_i differentiated at the
+// nodes along om_s, the s-th mode other than i.  One block per plane (mode
+// l = om_s by mode i, the remaining modes fixed): the plane of V_i goes to
+// LDS, G = V Dx^T along mode i, then Dd G along l; the s = 0 planes also
+// write slot 0.
+__global__ __launch_bounds__(256) void k_taylor(const Inst *__restrict__ tab, int bpi)
 {
     const InstView I = inst_view(tab, blockIdx.x / bpi);
     const int blk = blockIdx.x % bpi;
     const GameConst *__restrict__ gc = I.gc;
     const GameStatus *st = I.st;
-    const double *Vbuf = I.V;
-    double *G = I.G;
-    __shared__ double Dm[kMaxN * (kMaxN + 1)];
-    if (st->converged) return;
-    const int N = gc->N, d = gc->d;
-    constexpr int LD = kMaxN + 1;
-    for (int e = threadIdx.x; e < N * N; e += blockDim.x) Dm[(e / N) * LD + e % N] = gc->Dx[(e / N) * kMaxN + e % N];
-    __syncthreads();
-    const int NN = (int)gc->NN;
-    const int t = blk * blockDim.x + threadIdx.x;
-    if (t >= d * NN) return;
-    const int i = t / NN, idx = t % NN;
-    int stride = 1;
-    for (int l = i + 1; l < d; ++l) stride *= N;
-    const int lo = (idx / stride) % N;
-    const double *src = Vbuf + (long long)st->cur * d * NN + (long long)i * NN + (idx - lo * stride);
-    double acc = 0.0;
-    for (int k = 0; k < N; ++k) acc = fma(Dm[lo * LD + k], src[(long long)k * stride], acc);
-    G[t] = acc;
-}
-
-// E[i][slot][jm][col]: slot 0 = G_i at (jm, col), slot 1 + s = G_i
-// differentiated at the nodes along mode om_s (the s-th mode other than i).
-// jm enumerates the modes other than i in increasing order; col = k_i.
-__global__ __launch_bounds__(256) void k_taylor_b(const Inst *__restrict__ tab, int bpi)
-{
-    const InstView I = inst_view(tab, blockIdx.x / bpi);
-    const int blk = blockIdx.x % bpi;
-    const GameConst *__restrict__ gc = I.gc;
-    const GameStatus *st = I.st;
-    const double *__restrict__ G = I.G;
     double *E = I.E;
-    __shared__ double Dm[kMaxN * (kMaxN + 1)];
-    if (st->converged) return;
-    const int N = gc->N, d = gc->d, NC = gc->NC;
     constexpr int LD = kMaxN + 1;
-    for (int e = threadIdx.x; e < N * N; e += blockDim.x) Dm[(e / N) * LD + e % N] = gc->Dd[(e / N) * kMaxN + e % N];
-    __syncthreads();
-    const int NN = (int)gc->NN, NM = NN / N;
-    const int t = blk * blockDim.x + threadIdx.x;
-    if (t >= d * d * NN) return;
-    const int col = t % N;
-    const int jm = (t / N) % NM;
-    const int slot = (t / NN) % d;
-    const int i = t / (NN * d);
-    // digits of the modes other than i (increasing order) from jm
+    __shared__ double Dx[kMaxN * LD];
+    __shared__ double Dd[kMaxN * LD];
+    __shared__ double X[kMaxN * LD];
+    __shared__ double Gp[kMaxN * LD];
+    if (st->converged) return;
+    const int N = gc->N, d = gc->d, NC = gc->NC, NN2 = N * N;
+    const long long NN = gc->NN;
+    const int NM = (int)(NN / N);
+    int nf = 1;
+    for (int q = 0; q < d - 2; ++q) nf *= N;
+    const int i = blk / ((d - 1) * nf);
+    const int s = (blk / nf) % (d - 1);
+    const int f = blk % nf;
+    int om[kMaxD];
+    for (int t = 0; t < d - 1; ++t) om[t] = t < i ? t : t + 1;
+    const int l = om[s];
+    // digits of the fixed modes (the other modes except l, increasing order) from f
     int dig[kMaxD];
     {
-        int rem = jm;
-        for (int l = d - 1; l >= 0; --l) {
-            if (l == i) continue;
-            dig[l] = rem % N;
+        int rem = f;
+        for (int t = d - 2; t >= 0; --t) {
+            if (t == s) continue;
+            dig[om[t]] = rem % N;
             rem /= N;
         }
-        dig[i] = col;
     }
-    int idx = 0;
-    for (int l = 0; l < d; ++l) idx = idx * N + dig[l];
-    const double *Gi = G + (long long)i * NN;
-    double v;
-    if (slot == 0) {
-        v = Gi[idx];
-    } else {
-        const int l = (slot - 1) < i ? slot - 1 : slot;  // om_{slot-1}
-        int stride = 1;
-        for (int m = l + 1; m < d; ++m) stride *= N;
-        const int jl = dig[l];
-        const double *src = Gi + (idx - jl * stride);
-        v = 0.0;
-        for (int k = 0; k < N; ++k) v = fma(Dm[jl * LD + k], src[k * stride], v);
+    long long stride[kMaxD];
+    stride[d - 1] = 1;
+    for (int q = d - 2; q >= 0; --q) stride[q] = stride[q + 1] * N;
+    long long base = 0;
+    for (int q = 0; q < d; ++q)
+        if (q != i && q != l) base += dig[q] * stride[q];
+    const double *Vi = I.V + (long long)st->cur * d * NN + (long long)i * NN;
+    for (int e = threadIdx.x; e < NN2; e += blockDim.x) {
+        const int r = e / N, c = e % N;  // r: node along l, c: node along i
+        Dx[r * LD + c] = gc->Dx[r * kMaxN + c];
+        Dd[r * LD + c] = gc->Dd[r * kMaxN + c];
+        X[r * LD + c] = Vi[base + r * stride[l] + c * stride[i]];
     }
-    E[(((long long)i * d + slot) * NM + jm) * NC + col] = v;
+    __syncthreads();
+    const int tid = threadIdx.x;
+    // G[r][ki] = sum_j Dx[ki][j] X[r][j]
+    for (int e = tid; e < NN2; e += 256) {
+        const int r = e / N, ki = e % N;
+        double acc = 0.0;
+        for (int j = 0; j < N; ++j) acc = fma(Dx[ki * LD + j], X[r * LD + j], acc);
+        Gp[r * LD + ki] = acc;
+    }
+    __syncthreads();
+    // jm of (jl = r): other-mode digits in increasing order
+    double *Ei = E + (long long)i * d * NM * NC;
+    for (int e = tid; e < NN2; e += 256) {
+        const int r = e / N, ki = e % N;
+        double acc = 0.0;
+        for (int k = 0; k < N; ++k) acc = fma(Dd[r * LD + k], Gp[k * LD + ki], acc);
+        int jm = 0;
+        for (int t = 0; t < d - 1; ++t) jm = jm * N + (t == s ? r : dig[om[t]]);
+        Ei[((long long)(1 + s) * NM + jm) * NC + ki] = acc;
+        if (s == 0) Ei[(long long)jm * NC + ki] = Gp[r * LD + ki];
+    }
 }
 
 hipError_t launch_taylor(const GameConst &hc, const StepBuffers &b, hipStream_t s)
 {
-    const int ba = (int)((hc.d * hc.NN + 255) / 256), bb = (int)(((long long)hc.d * hc.d * hc.NN + 255) / 256);
-    hipLaunchKernelGGL(k_taylor_a, dim3((unsigned)(ba * b.count)), dim3(256), 0, s, b.tab, ba);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_taylor_b, dim3((unsigned)(bb * b.count)), dim3(256), 0, s, b.tab, bb);
+    int nf = 1;
+    for (int q = 0; q < hc.d - 2; ++q) nf *= hc.N;
+    const int bpi = hc.d * (hc.d - 1) * nf;
+    hipLaunchKernelGGL(k_taylor, dim3((unsigned)(bpi * b.count)), dim3(256), 0, s, b.tab, bpi);
     return hipGetLastError();
 }
 
