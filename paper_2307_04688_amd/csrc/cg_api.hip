@@ -53,7 +53,7 @@ int check_device()
 }
 
 struct Layout {
-    size_t gc, st, tab, V, U, coef, tmp, Bp, W, Bp32, E, G, total;
+    size_t gc, st, tab, V, U, coef, tmp, Bp, W, Bp32, E, blk, total;
 };
 
 int validate(const cg_game_desc *g, int precision)
@@ -114,11 +114,11 @@ Layout layout(const cg_game_desc *g, int precision)
     L.tmp = o; o = align256(o + sizeof(double) * g->d * NN);
     L.Bp = o; o = align256(o + sizeof(double) * (size_t)g->d * K * NC);
     L.W = o; o = align256(o + sizeof(double) * (size_t)g->d * NN * NC);
-    L.Bp32 = L.E = L.G = 0;
+    L.blk = o; o = align256(o + sizeof(double) * (size_t)g->d * ((NN + 63) / 64));
+    L.Bp32 = L.E = 0;
     if (precision == CG_FP32_CORR) {
         L.Bp32 = o; o = align256(o + sizeof(float) * (size_t)g->d * K * NC);
         L.E = o; o = align256(o + sizeof(double) * (size_t)g->d * g->d * (NN / g->n_nodes) * NC);
-        L.G = o; o = align256(o + sizeof(double) * (size_t)g->d * NN);
     }
     L.total = o;
     return L;
@@ -209,7 +209,7 @@ Inst inst_offsets(const InstPtrs &p, const void *table_dev)
     e.W = off(p.W);
     e.Bp32 = off(p.Bp32);
     e.E = off(p.E);
-    e.G = off(p.G);
+    e.blk = off(p.blk);
     return e;
 }
 int game_precision(const cg_game *g) { return g->precision; }
@@ -405,7 +405,7 @@ int cg_init_game(const cg_game_desc *g, int precision, void *ws_dev, size_t ws_b
     b.W = (double *)(G->ws + L.W);
     b.Bp32 = precision == CG_FP32_CORR ? (float *)(G->ws + L.Bp32) : nullptr;
     b.E = precision == CG_FP32_CORR ? (double *)(G->ws + L.E) : nullptr;
-    b.G = precision == CG_FP32_CORR ? (double *)(G->ws + L.G) : nullptr;
+    b.blk = (double *)(G->ws + L.blk);
     b.precision = precision;
     b.ev_begin = b.ev_end = nullptr;
     b.tab = (const Inst *)(G->ws + L.tab);
@@ -422,7 +422,7 @@ int cg_init_game(const cg_game_desc *g, int precision, void *ws_dev, size_t ws_b
     hi.W = b.W;
     hi.Bp32 = b.Bp32;
     hi.E = b.E;
-    hi.G = b.G;
+    hi.blk = b.blk;
     G->prof = false;
     G->ev_used = 0;
 

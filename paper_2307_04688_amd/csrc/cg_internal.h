@@ -68,7 +68,8 @@ struct InstPtrs {
     double *Bp;              // packed operand (FP64)
     double *W;               // line coefficients
     float *Bp32;             // packed operand (binary32, FP32_CORR)
-    double *E, *G;           // FP32_CORR tensors
+    double *E;               // FP32_CORR Taylor tensors
+    double *blk;             // per-block residual maxima of the line kernel
 };
 
 // Entry of a device table of instances: the same pointers as byte offsets
@@ -78,7 +79,7 @@ struct InstPtrs {
 // kernel argument) plus an offset are known to the compiler to be global
 // memory, so loads and stores through them are global (not flat) accesses.
 struct Inst {
-    long long gc, st, V, U, coef, tmp, Bp, W, Bp32, E, G;
+    long long gc, st, V, U, coef, tmp, Bp, W, Bp32, E, blk;
 };
 Inst inst_offsets(const InstPtrs &p, const void *table_dev);
 
@@ -87,7 +88,7 @@ struct InstView {
     GameStatus *st;
     double *V, *U, *coef, *tmp, *Bp, *W;
     float *Bp32;
-    double *E, *G;
+    double *E, *blk;
 };
 __device__ __forceinline__ InstView inst_view(const Inst *tab, int k)
 {
@@ -104,7 +105,7 @@ __device__ __forceinline__ InstView inst_view(const Inst *tab, int k)
     v.W = (double *)(b + e.W);
     v.Bp32 = (float *)(b + e.Bp32);
     v.E = (double *)(b + e.E);
-    v.G = (double *)(b + e.G);
+    v.blk = (double *)(b + e.blk);
     return v;
 }
 
@@ -119,7 +120,7 @@ struct StepBuffers {
     double *W;               // d * NN * NC line coefficients (contraction output)
     float *Bp32;             // d * K * NC packed operand in binary32 (FP32_CORR)
     double *E;               // FP32_CORR: [d][d][N^(d-1)][NC] value / first-order tensors
-    double *G;               // FP32_CORR: [d][N^d] V_i transformed along mode i
+    double *blk;             // per-block residual maxima of the line kernel (d ceil(N^d / 64))
     int precision;
     hipEvent_t ev_begin, ev_end;  // recorded around the contraction kernel when non-null
     const Inst *tab;              // device table of the instances of this launch

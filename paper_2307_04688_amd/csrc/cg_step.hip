@@ -232,7 +232,8 @@ __device__ void finish_step(const GameConst *__restrict__ gc, GameStatus *st, in
 // each samples half of the control nodes, and the partial fits are summed
 // through LDS.
 template <int D, int N4, int NC, bool COMPOSE>
-__global__ __launch_bounds__(256) void k_line_f64(const Inst *__restrict__ tab, int bpi, int blocks_per_player)
+__global__ __launch_bounds__(COMPOSE ? 64 : 256) void k_line_f64(const Inst *__restrict__ tab, int bpi,
+                                                                  int blocks_per_player)
 {
     const InstView I = inst_view(tab, blockIdx.x / bpi);
     const int blk = blockIdx.x % bpi;
@@ -240,10 +241,14 @@ __global__ __launch_bounds__(256) void k_line_f64(const Inst *__restrict__ tab, 
     GameStatus *st = I.st;
     double *Vbuf = I.V, *Ubuf = I.U;
     const double *__restrict__ Win = I.W;
+    // one wave per block when a thread owns a row: the few waves of a step
+    // spread evenly over the SIMDs
     constexpr int TPR = COMPOSE ? 1 : 2;
-    constexpr int ROWS_B = 256 / TPR;
+    constexpr int BT = COMPOSE ? 64 : 256;
+    constexpr int ROWS_B = BT / TPR;
+    constexpr int NWB = BT / 64;
     __shared__ double Qx[COMPOSE ? 1 : N4 * ROWS_B];
-    __shared__ double red[4];
+    __shared__ double red[NWB];
 
     if (st->converged) return;
     const int cur = st->cur;
@@ -305,18 +310,41 @@ __global__ __launch_bounds__(256) void k_line_f64(const Inst *__restrict__ tab, 
     }
     if (lane == 0) red[wave] = __longlong_as_double(bits);
     __syncthreads();
-    if (tid == 0) {
+    if (tid == 0) {  // this block's maximum; k_finish reduces them (no same-address atomics)
         unsigned long long m = 0;
-        for (int w2 = 0; w2 < 4; ++w2) {
+        for (int w2 = 0; w2 < NWB; ++w2) {
             const unsigned long long x = __double_as_longlong(red[w2]);
             m = x > m ? x : m;
         }
-        atomicMax(&st->res_bits[cur], m);
-        __threadfence();
-        if (atomicAdd(&st->blocks_done, 1u) == (unsigned)bpi - 1u) {
-            __threadfence();
-            finish_step(gc, st, cur);
-        }
+        I.blk[blk] = __longlong_as_double(m);
+    }
+}
+
+// End of an iteration, one block per instance: the residual is the bitwise
+// maximum of the line kernel's per-block maxima, reduced in a fixed order;
+// then the status bookkeeping.
+__global__ __launch_bounds__(256) void k_finish(const Inst *__restrict__ tab, int nblk)
+{
+    const InstView I = inst_view(tab, blockIdx.x);
+    GameStatus *st = I.st;
+    __shared__ unsigned long long red[256];
+    if (st->converged) return;
+    const int tid = threadIdx.x;
+    unsigned long long m = 0;
+    for (int k = tid; k < nblk; k += 256) {
+        const unsigned long long x = __double_as_longlong(I.blk[k]);
+        m = x > m ? x : m;
+    }
+    red[tid] = m;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (tid < w) red[tid] = red[tid + w] > red[tid] ? red[tid + w] : red[tid];
+        __syncthreads();
+    }
+    if (tid == 0) {
+        const int cur = st->cur;
+        st->res_bits[cur] = red[0];
+        finish_step(I.gc, st, cur);
     }
 }
 
@@ -365,15 +393,19 @@ static hipError_t launch_step_dn(const GameConst &hc, const StepBuffers &b, hipS
         if (e != hipSuccess) return e;
     }
     if (hc.Nu >= hc.N) {  // the fit in u is exact: compose the series directly
-        const int lpp = (NN + 255) / 256;
+        const int lpp = (NN + 63) / 64;
         const int bpi = lpp * D;
-        hipLaunchKernelGGL((k_line_f64<D, N4, NC, true>), dim3((unsigned)(bpi * b.count)), dim3(256), 0, s, b.tab,
+        hipLaunchKernelGGL((k_line_f64<D, N4, NC, true>), dim3((unsigned)(bpi * b.count)), dim3(64), 0, s, b.tab,
                            bpi, lpp);
+        e = hipGetLastError();
+        if (e == hipSuccess) hipLaunchKernelGGL(k_finish, dim3((unsigned)b.count), dim3(256), 0, s, b.tab, bpi);
     } else {
         const int lpp = (NN + 127) / 128;
         const int bpi = lpp * D;
         hipLaunchKernelGGL((k_line_f64<D, N4, NC, false>), dim3((unsigned)(bpi * b.count)), dim3(256), 0, s, b.tab,
                            bpi, lpp);
+        e = hipGetLastError();
+        if (e == hipSuccess) hipLaunchKernelGGL(k_finish, dim3((unsigned)b.count), dim3(256), 0, s, b.tab, bpi);
     }
     return hipGetLastError();
 }
