@@ -137,6 +137,32 @@ hipError_t launch_eval(int d, const int *n, const double *coef, const double *x,
                        void *out, int precision, void *ws, size_t ws_bytes, hipStream_t s);
 size_t eval_ws_bytes(int d, const int *n, int precision);
 
+// One 16 x 16 tile of C = op(A) op(B) (NP x NP, NP = 16 or 32) with both
+// operands in LDS (row stride LD doubles, zero beyond the data), on
+// v_mfma_f64_16x16x4f64.  Wave w < (NP/16)^2 computes tile (ti, tj) = (w / T,
+// w % T); element v of lane r16 + 16 kq holds C[16 ti + kq + 4 v][16 tj + r16].
+// TA: A[r][k] is stored at a[k LD + r]; TB: B[k][c] at b[c LD + k].
+template <int NP, int LD, bool TA, bool TB>
+__device__ __forceinline__ bool plane_mfma(const double *a, const double *b, int wave, int lane, f64x4 &acc, int &ti,
+                                           int &tj)
+{
+    constexpr int T = NP / 16;
+    if (wave >= T * T) return false;
+    ti = wave / T;
+    tj = wave % T;
+    const int r16 = lane & 15, kq = lane >> 4;
+    const int ra = ti * 16 + r16, cb = tj * 16 + r16;
+    acc = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int ks = 0; ks < NP / 4; ++ks) {
+        const int k = ks * 4 + kq;
+        const double av = TA ? a[k * LD + ra] : a[ra * LD + k];
+        const double bv = TB ? b[cb * LD + k] : b[k * LD + cb];
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+    }
+    return true;
+}
+
 // Accessors of a game handle for the batch code (defined with the handle).
 const GameConst &game_consts(const cg_game *g);
 const InstPtrs &game_inst(const cg_game *g);

@@ -33,6 +33,7 @@ namespace cg {
 // l = om_s by mode i, the remaining modes fixed): the plane of V_i goes to
 // LDS, G = V Dx^T along mode i, then Dd G along l; the s = 0 planes also
 // write slot 0.
+template <int NP>
 __global__ __launch_bounds__(256) void k_taylor(const Inst *__restrict__ tab, int bpi)
 {
     const InstView I = inst_view(tab, blockIdx.x / bpi);
@@ -46,7 +47,7 @@ __global__ __launch_bounds__(256) void k_taylor(const Inst *__restrict__ tab, in
     __shared__ double X[kMaxN * LD];
     __shared__ double Gp[kMaxN * LD];
     if (st->converged) return;
-    const int N = gc->N, d = gc->d, NC = gc->NC, NN2 = N * N;
+    const int N = gc->N, d = gc->d, NC = gc->NC;
     const long long NN = gc->NN;
     const int NM = (int)(NN / N);
     int nf = 1;
@@ -74,32 +75,36 @@ __global__ __launch_bounds__(256) void k_taylor(const Inst *__restrict__ tab, in
     for (int q = 0; q < d; ++q)
         if (q != i && q != l) base += dig[q] * stride[q];
     const double *Vi = I.V + (long long)st->cur * d * NN + (long long)i * NN;
-    for (int e = threadIdx.x; e < NN2; e += blockDim.x) {
-        const int r = e / N, c = e % N;  // r: node along l, c: node along i
-        Dx[r * LD + c] = gc->Dx[r * kMaxN + c];
-        Dd[r * LD + c] = gc->Dd[r * kMaxN + c];
-        X[r * LD + c] = Vi[base + r * stride[l] + c * stride[i]];
+    for (int e = threadIdx.x; e < NP * NP; e += blockDim.x) {  // zero beyond N
+        const int r = e / NP, c = e % NP;  // r: node along l, c: node along i
+        const bool in = r < N && c < N;
+        Dx[r * LD + c] = in ? gc->Dx[r * kMaxN + c] : 0.0;
+        Dd[r * LD + c] = in ? gc->Dd[r * kMaxN + c] : 0.0;
+        X[r * LD + c] = in ? Vi[base + r * stride[l] + c * stride[i]] : 0.0;
     }
     __syncthreads();
-    const int tid = threadIdx.x;
-    // G[r][ki] = sum_j Dx[ki][j] X[r][j]
-    for (int e = tid; e < NN2; e += 256) {
-        const int r = e / N, ki = e % N;
-        double acc = 0.0;
-        for (int j = 0; j < N; ++j) acc = fma(Dx[ki * LD + j], X[r * LD + j], acc);
-        Gp[r * LD + ki] = acc;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int r16 = lane & 15, kq = lane >> 4;
+    f64x4 acc;
+    int ti, tj;
+    // G[r][ki] = sum_j X[r][j] Dx[ki][j]
+    if (plane_mfma<NP, LD, false, true>(X, Dx, wave, lane, acc, ti, tj)) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Gp[(ti * 16 + kq + 4 * v) * LD + tj * 16 + r16] = acc[v];
     }
     __syncthreads();
-    // jm of (jl = r): other-mode digits in increasing order
+    // E_l[r][ki] = sum_k Dd[r][k] G[k][ki]
     double *Ei = E + (long long)i * d * NM * NC;
-    for (int e = tid; e < NN2; e += 256) {
-        const int r = e / N, ki = e % N;
-        double acc = 0.0;
-        for (int k = 0; k < N; ++k) acc = fma(Dd[r * LD + k], Gp[k * LD + ki], acc);
-        int jm = 0;
-        for (int t = 0; t < d - 1; ++t) jm = jm * N + (t == s ? r : dig[om[t]]);
-        Ei[((long long)(1 + s) * NM + jm) * NC + ki] = acc;
-        if (s == 0) Ei[(long long)jm * NC + ki] = Gp[r * LD + ki];
+    if (plane_mfma<NP, LD, false, false>(Dd, Gp, wave, lane, acc, ti, tj)) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int r = ti * 16 + kq + 4 * v, ki = tj * 16 + r16;
+            if (r >= N || ki >= N) continue;
+            int jm = 0;
+            for (int t = 0; t < d - 1; ++t) jm = jm * N + (t == s ? r : dig[om[t]]);
+            Ei[((long long)(1 + s) * NM + jm) * NC + ki] = acc[v];
+            if (s == 0) Ei[(long long)jm * NC + ki] = Gp[r * LD + ki];
+        }
     }
 }
 
@@ -108,7 +113,10 @@ hipError_t launch_taylor(const GameConst &hc, const StepBuffers &b, hipStream_t 
     int nf = 1;
     for (int q = 0; q < hc.d - 2; ++q) nf *= hc.N;
     const int bpi = hc.d * (hc.d - 1) * nf;
-    hipLaunchKernelGGL(k_taylor, dim3((unsigned)(bpi * b.count)), dim3(256), 0, s, b.tab, bpi);
+    if (hc.N <= 16)
+        hipLaunchKernelGGL(k_taylor<16>, dim3((unsigned)(bpi * b.count)), dim3(256), 0, s, b.tab, bpi);
+    else
+        hipLaunchKernelGGL(k_taylor<32>, dim3((unsigned)(bpi * b.count)), dim3(256), 0, s, b.tab, bpi);
     return hipGetLastError();
 }
 

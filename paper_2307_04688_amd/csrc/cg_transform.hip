@@ -94,6 +94,7 @@ __device__ __forceinline__ long long packed_index(const GameConst *__restrict__ 
     return ((long long)i * gc->K + (long long)kout * gc->N4 + kl) * gc->NC + col;
 }
 
+template <int NP>
 __global__ __launch_bounds__(256) void k_tf_fast(const Inst *__restrict__ tab, int bpi, int mixed)
 {
     const InstView I = inst_view(tab, blockIdx.x / bpi);
@@ -113,57 +114,34 @@ __global__ __launch_bounds__(256) void k_tf_fast(const Inst *__restrict__ tab, i
     const int nslice = (int)(NN / NN2);
     const int i = blk / nslice, sl = blk % nslice;
     const double *src = Vbuf + (long long)st->cur * d * NN + (long long)i * NN + (long long)sl * NN2;
-    for (int e = threadIdx.x; e < NN2; e += blockDim.x) {
-        Dm[(e / N) * LD + e % N] = gc->Dx[(e / N) * kMaxN + e % N];
-        X[(e / N) * LD + e % N] = src[e];
+    for (int e = threadIdx.x; e < NP * NP; e += blockDim.x) {  // zero beyond N
+        const int r = e / NP, c = e % NP;
+        const bool in = r < N && c < N;
+        Dm[r * LD + c] = in ? gc->Dx[r * kMaxN + c] : 0.0;
+        X[r * LD + c] = in ? src[r * N + c] : 0.0;
     }
     __syncthreads();
-    // Y = D X (mode d-2), then Z = Y D^T (mode d-1).  Each thread owns the
-    // outputs e = tid + 256 u, u < 4 (N^2 <= 1024), run as four independent
-    // accumulation chains.
-    const int tid = threadIdx.x;
-    {
-        double acc[4] = {0.0, 0.0, 0.0, 0.0};
-        int lrow[4], ccol[4];
+    // Y = D X (mode d-2), then Z = Y D^T (mode d-1), on FP64 MFMA
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int r16 = lane & 15, kq = lane >> 4;
+    f64x4 acc;
+    int ti, tj;
+    if (plane_mfma<NP, LD, false, false>(Dm, X, wave, lane, acc, ti, tj)) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int e = tid + 256 * u;
-            lrow[u] = e < NN2 ? e / N : 0;
-            ccol[u] = e < NN2 ? e % N : 0;
-        }
-        for (int k = 0; k < N; ++k) {
-            const double *Xk = X + k * LD;
-#pragma unroll
-            for (int u = 0; u < 4; ++u) acc[u] = fma(Dm[lrow[u] * LD + k], Xk[ccol[u]], acc[u]);
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-            if (tid + 256 * u < NN2) Y[lrow[u] * LD + ccol[u]] = acc[u];
+        for (int v = 0; v < 4; ++v) Y[(ti * 16 + kq + 4 * v) * LD + tj * 16 + r16] = acc[v];
     }
     __syncthreads();
-    {
-        double acc[4] = {0.0, 0.0, 0.0, 0.0};
-        int rrow[4], lcol[4];
+    if (plane_mfma<NP, LD, false, true>(Y, Dm, wave, lane, acc, ti, tj)) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int e = tid + 256 * u;
-            rrow[u] = e < NN2 ? e / N : 0;
-            lcol[u] = e < NN2 ? e % N : 0;
-        }
-        for (int k = 0; k < N; ++k) {
-#pragma unroll
-            for (int u = 0; u < 4; ++u) acc[u] = fma(Y[rrow[u] * LD + k], Dm[lcol[u] * LD + k], acc[u]);
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int e = tid + 256 * u;
-            if (e >= NN2) continue;
+        for (int v = 0; v < 4; ++v) {
+            const int r = ti * 16 + kq + 4 * v, c = tj * 16 + r16;
+            if (r >= N || c >= N) continue;
             if (d > 2) {
-                out[(long long)i * NN + (long long)sl * NN2 + e] = acc[u];
+                out[(long long)i * NN + (long long)sl * NN2 + r * N + c] = acc[v];
             } else {
-                int dig[kMaxD] = {rrow[u], lcol[u], 0, 0};
+                int dig[kMaxD] = {r, c, 0, 0};
                 const long long o = packed_index(gc, i, dig);
-                if (Bp32) Bp32[o] = (float)acc[u]; else Bp[o] = acc[u];
+                if (Bp32) Bp32[o] = (float)acc[v]; else Bp[o] = acc[v];
             }
         }
     }
@@ -234,7 +212,10 @@ hipError_t launch_transform_game(const GameConst &hc, const StepBuffers &b, hipS
     const int mixed = b.precision == CG_FP32_CORR;  // packed operand in binary32
     const long long nslice = hc.NN / (N * N);
     const int bpi1 = (int)(nslice * d);
-    hipLaunchKernelGGL(k_tf_fast, dim3((unsigned)(bpi1 * b.count)), dim3(256), 0, s, b.tab, bpi1, mixed);
+    if (N <= 16)
+        hipLaunchKernelGGL(k_tf_fast<16>, dim3((unsigned)(bpi1 * b.count)), dim3(256), 0, s, b.tab, bpi1, mixed);
+    else
+        hipLaunchKernelGGL(k_tf_fast<32>, dim3((unsigned)(bpi1 * b.count)), dim3(256), 0, s, b.tab, bpi1, mixed);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || d == 2) return e;
     // Q inner positions per tile, so that the dynamic LDS (D plus one or two
