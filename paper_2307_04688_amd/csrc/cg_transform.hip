@@ -206,6 +206,50 @@ __global__ __launch_bounds__(256) void k_tf_outer(const Inst *__restrict__ tab, 
     }
 }
 
+// d = 3: mode 0 on FP64 MFMA.  Block = (player, NP consecutive inner
+// positions q of the two fast modes): Out[l][q] = sum_k D[l][k] X[k][q], then
+// the packed operand.
+template <int NP>
+__global__ __launch_bounds__(256) void k_tf_mode0(const Inst *__restrict__ tab, int bpi, int mixed)
+{
+    const InstView I = inst_view(tab, blockIdx.x / bpi);
+    const int blk = blockIdx.x % bpi;
+    const GameConst *__restrict__ gc = I.gc;
+    const GameStatus *st = I.st;
+    const double *__restrict__ in = I.tmp;
+    double *Bp = I.Bp;
+    float *Bp32 = mixed ? I.Bp32 : nullptr;
+    constexpr int LD = kMaxN + 1;
+    __shared__ double Dm[kMaxN * LD];
+    __shared__ double X[kMaxN * LD];
+    if (st->converged) return;
+    const int N = gc->N, NN2 = N * N;
+    const long long NN = gc->NN;
+    const int nq = (NN2 + NP - 1) / NP;
+    const int i = blk / nq, q0 = (blk % nq) * NP;
+    const double *src = in + (long long)i * NN;
+    for (int e = threadIdx.x; e < NP * NP; e += blockDim.x) {  // zero beyond N and NN2
+        const int r = e / NP, c = e % NP;
+        Dm[r * LD + c] = (r < N && c < N) ? gc->Dx[r * kMaxN + c] : 0.0;
+        X[r * LD + c] = (r < N && q0 + c < NN2) ? src[(long long)r * NN2 + q0 + c] : 0.0;
+    }
+    __syncthreads();
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int r16 = lane & 15, kq = lane >> 4;
+    f64x4 acc;
+    int ti, tj;
+    if (plane_mfma<NP, LD, false, false>(Dm, X, wave, lane, acc, ti, tj)) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int l = ti * 16 + kq + 4 * v, q = q0 + tj * 16 + r16;
+            if (l >= N || q >= NN2) continue;
+            int dig[kMaxD] = {l, q / N, q % N, 0};
+            const long long o = packed_index(gc, i, dig);
+            if (Bp32) Bp32[o] = (float)acc[v]; else Bp[o] = acc[v];
+        }
+    }
+}
+
 hipError_t launch_transform_game(const GameConst &hc, const StepBuffers &b, hipStream_t s)
 {
     const int N = hc.N, d = hc.d;
@@ -218,6 +262,15 @@ hipError_t launch_transform_game(const GameConst &hc, const StepBuffers &b, hipS
         hipLaunchKernelGGL(k_tf_fast<32>, dim3((unsigned)(bpi1 * b.count)), dim3(256), 0, s, b.tab, bpi1, mixed);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || d == 2) return e;
+    if (d == 3) {
+        const int NP = N <= 16 ? 16 : 32;
+        const int bpi3 = d * ((N * N + NP - 1) / NP);
+        if (NP == 16)
+            hipLaunchKernelGGL(k_tf_mode0<16>, dim3((unsigned)(bpi3 * b.count)), dim3(256), 0, s, b.tab, bpi3, mixed);
+        else
+            hipLaunchKernelGGL(k_tf_mode0<32>, dim3((unsigned)(bpi3 * b.count)), dim3(256), 0, s, b.tab, bpi3, mixed);
+        return hipGetLastError();
+    }
     // Q inner positions per tile, so that the dynamic LDS (D plus one or two
     // F x Q tiles) stays within 64 KiB
     const int F = (int)nslice;
