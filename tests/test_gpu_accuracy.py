@@ -1,0 +1,47 @@
+"""The GPU iteration against the continuous-time equilibrium of the 2-player
+linear-quadratic game: first-order convergence in h, as the oracle shows."""
+import numpy as np
+import pytest
+
+import riccati
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def cg():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2307_04688_amd import chebgame
+    chebgame.lib()
+    return chebgame
+
+
+def nodes_phys(orc, g):
+    x = orc.nodes(g.N)
+    return np.stack(np.meshgrid(*([x] * g.d), indexing="ij")).reshape(g.d, -1) * 0.5 * g.p_max + 0.5 * g.p_max
+
+
+def test_first_order_in_h_on_gpu(cg, orc):
+    print("accuracy study on the GPU", flush=True)
+    errs, ustar = [], None
+    for h in (0.1, 0.05, 0.025, 0.0125):
+        g = W.make_game(2, 5, seed=1, nominal=True, h=h, p_max=0.5)
+        G = cg.ChebGame(g, cg.FP64)
+        rc, n, r = G.solve(100000, 1e-12)
+        assert rc == cg.OK
+        V, U, _ = G.get_state()
+        V, U = V.cpu().numpy(), U.cpu().numpy()
+        P = nodes_phys(orc, g)
+        if ustar is None:
+            sol, rmax = riccati.solve(g, V, P)
+            assert rmax < 1e-12
+            ustar = riccati.policy(sol, g, P)
+            Vo, Uo, _ = orc.solve(g, 100000, tol=1e-12)
+            assert np.max(np.abs(U - Uo)) < 1e-9           # GPU and oracle reach the same fixed point
+        errs.append(np.max(np.abs(U - ustar)))
+    rates = [errs[k] / errs[k + 1] for k in range(len(errs) - 1)]
+    print("  max policy error", errs, "ratios", rates, flush=True)
+    assert all(1.7 < q < 2.3 for q in rates)
