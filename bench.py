@@ -343,6 +343,48 @@ def run_sim(cg, W, torch, steps: int, warmup: int, n_paths: int = 1024, n_steps:
             "final_mean_state": paths[:, -1].mean(dim=0).tolist()}
 
 
+def run_accuracy(cg, W, torch):
+    """The error study of Section 4.1 (its Chebyshev half) on the GPU: the
+    2-player game with the example's nominal parameters, P_M = 0.5 (the policy
+    stays inside (0, U_M)), N^p in {2, 4, 8} (N = N^p + 1 nodes), h in {1e-1,
+    1e-2, 1e-3}, TOL in {1e-3 .. 1e-6}.  Error of the final policy against the
+    continuous-time equilibrium (quadratic value functions from the HJB
+    equation, tests/riccati.py) at the nodes, with the paper's normalisation
+    (1/N_Psi) sqrt(sum (u* - u)^2), and the maximum; time per solve."""
+    import numpy as np
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    import riccati
+
+    def nodes_phys(g):
+        x = np.cos(np.pi * np.arange(g.N) / (g.N - 1))
+        return np.stack(np.meshgrid(*([x] * g.d), indexing="ij")).reshape(g.d, -1) * 0.5 * g.p_max + 0.5 * g.p_max
+
+    g0 = W.make_game(2, 5, seed=1, nominal=True, h=0.0125, p_max=0.5)
+    G0 = cg.ChebGame(g0, cg.FP64)
+    G0.solve(200000, 1e-13)
+    sol, hjb = riccati.solve(g0, G0.get_state()[0].cpu().numpy(), nodes_phys(g0))
+    rows = []
+    for N in (3, 5, 9):
+        for h in (1e-1, 1e-2, 1e-3):
+            for tol in (1e-3, 1e-4, 1e-5, 1e-6):
+                g = W.make_game(2, N, seed=1, nominal=True, h=h, p_max=0.5)
+                G = cg.ChebGame(g, cg.FP64)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                rc, n, r = G.solve(400000, tol)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                U = G.get_state()[1].cpu().numpy()
+                e = U - riccati.policy(sol, g, nodes_phys(g))
+                rows.append({"Np": N - 1, "h": h, "tol": tol, "iterations": n, "converged": rc == cg.OK,
+                             "seconds": dt, "error_paper": float(np.sqrt(np.sum(e * e)) / e.size),
+                             "error_max": float(np.max(np.abs(e)))})
+                print(f"bench: N^p={N - 1} h={h} tol={tol}: {n} iterations, {dt:.3f} s, max error "
+                      f"{rows[-1]['error_max']:.2e}", file=sys.stderr, flush=True)
+    return {"workload": "2-player LQ game (Section 4.1 example), error vs continuous-time equilibrium",
+            "hjb_residual_of_reference": hjb, "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -351,7 +393,8 @@ def main():
     ap.add_argument("--precision", default="fp32corr", choices=["fp64", "fp32corr"],
                     help="path reported as value; the other is timed beside it")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "batch", "warm", "eval", "sim"])
+    ap.add_argument("--workload", default="c2",
+                    choices=["c2", "c3", "batch", "warm", "eval", "sim", "accuracy"])
     ap.add_argument("--cpu-steps", type=int, default=6, help="oracle iterations timed for the CPU baseline")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for scaling rocprof byte counters)")
@@ -370,6 +413,9 @@ def main():
     if args.workload == "batch":
         print("bench: ragged batch of 256 games", file=sys.stderr, flush=True)
         print(json.dumps(run_batch(cg, W, torch, args.steps, args.warmup)), flush=True)
+        return
+    if args.workload == "accuracy":
+        print(json.dumps(run_accuracy(cg, W, torch)), flush=True)
         return
     if args.workload == "sim":
         print(json.dumps(run_sim(cg, W, torch, args.steps, args.warmup)), flush=True)
