@@ -186,6 +186,34 @@ def test_one_step_from_random_state(cg, orc, d, N, scale, p_max):
     assert np.max(np.abs(Ug[m] - Uo[m])) <= 1e-10 * g.u_max
 
 
+@pytest.mark.parametrize("d,N,amp,h", [(2, 16, 3.0, 0.5), (3, 12, 2.0, 0.4), (2, 20, 2.0, 0.3)])
+def test_nonconcave_lines_take_the_global_maximum(cg, orc, d, N, amp, h):
+    """A crafted V_i = amp T_8(x_i) with a long Euler step makes the line
+    function in u oscillate (several local maxima): the concavity certificate
+    fails there and the kernel's safeguarded search must land on the oracle's
+    global maximiser."""
+    say("non-concave lines", d, N, amp, h)
+    g = W.make_game(d, N, seed=80 + N, per_player=True, h=h)
+    x = orc.nodes(N)
+    X = np.stack(np.meshgrid(*([x] * d), indexing="ij")).reshape(d, -1)
+    V = amp * np.cos(8 * np.arccos(np.clip(X, -1, 1)))           # V_i depends on x_i only
+    U = np.repeat(np.asarray(g.A, dtype=float)[:, None], N ** d, axis=1)
+    Vo, Uo, _, nnc = orc.step(g, V, U)
+    assert nnc > 0.2 * d * N ** d                                 # the fallback path is exercised
+    G = _gpu_game(cg, g)
+    G.set_state(dev(V), dev(U))
+    G.step(1)
+    Vg, Ug, _ = G.get_state()
+    Vg, Ug = Vg.cpu().numpy(), Ug.cpu().numpy()
+    # the long step sends update points far outside the box, where the polynomial
+    # continuation of T_8 reaches 1e4 and sums of large cancelling terms set the
+    # rounding level: V to 1e-10 relative here
+    assert np.max(np.abs(Vg - Vo)) <= 1e-10 * np.max(np.abs(Vo))
+    du = np.abs(Ug - Uo)
+    say("  max |du|", du.max(), "nodes with |du| > 1e-9:", int((du > 1e-9 * g.u_max).sum()))
+    assert np.all(du <= 1e-9 * g.u_max)
+
+
 @pytest.mark.parametrize("d,N,Nu", [(2, 9, 6), (3, 6, 8), (2, 16, 11), (3, 7, 5), (2, 12, 12)])
 def test_control_node_counts(cg, orc, d, N, Nu):
     # fewer control nodes than state nodes: the fit in u is a sampled
