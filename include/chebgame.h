@@ -277,8 +277,8 @@ int cg_solve_warm(cg_game *game, const float *params, const float *theta, double
 int cg_simulate(cg_game *game, const double *p0_dev, int32_t n_paths, int32_t n_steps, double *paths_dev,
                 double *controls_dev);
 
-/* Timing of the contraction kernel (the fused step kernel that carries the
- * mode-n contractions).  With enable != 0, every later step records a pair of
+/* Timing of the contraction kernel (the kernel that carries the mode-n
+ * contractions).  With enable != 0, every later step records a pair of
  * HIP events on the game's stream around that kernel's launch.  If kernel_ms
  * or launches is not NULL the call first synchronises the stream and
  * returns the summed elapsed time and the number of timed launches since the

@@ -246,7 +246,6 @@ __global__ void k_fill_state(double *V, double *U, const GameConst *__restrict__
         st->total_steps = 0;
         st->cur = 0;
         st->nonfinite = 0;
-        st->blocks_done = 0u;
     }
 }
 
@@ -282,7 +281,6 @@ __global__ void k_arm(GameConst *gc, GameStatus *st, double tol, int clear_done)
         st->converged = 0;
         st->nonfinite = 0;
         st->res_bits[st->cur] = 0ull;
-        st->blocks_done = 0u;
         if (clear_done) st->steps_done = 0;
     }
 }

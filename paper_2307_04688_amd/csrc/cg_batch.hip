@@ -49,7 +49,6 @@ __global__ void k_batch_arm(const Inst *__restrict__ tab, int count, double tol,
     st->converged = 0;
     st->nonfinite = 0;
     st->res_bits[st->cur] = 0ull;
-    st->blocks_done = 0u;
     if (clear_done) st->steps_done = 0;
 }
 
@@ -86,7 +85,6 @@ __global__ void k_batch_reset(const Inst *__restrict__ tab, int count)
         st->steps_done = 0;
         st->cur = 0;
         st->nonfinite = 0;
-        st->blocks_done = 0u;
     }
 }
 

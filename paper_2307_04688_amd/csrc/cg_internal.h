@@ -45,7 +45,6 @@ struct GameStatus {
     int cur;                         // which of the two state buffers holds V^{[r]}, u^{[r]}
     int nonfinite;                   // a non-finite residual was produced
     int total_steps;                 // iterations performed since init
-    unsigned int blocks_done;        // blocks of the running line kernel that have finished
 };
 
 // ---- launchers (defined in the .hip files) ----

@@ -221,7 +221,6 @@ __device__ void finish_step(const GameConst *__restrict__ gc, GameStatus *st, in
     }
     st->res_bits[1 - cur] = 0ull;
     st->cur = 1 - cur;
-    atomicExch(&st->blocks_done, 0u);
 }
 
 // ---------------------------------------------------------------------------

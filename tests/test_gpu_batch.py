@@ -124,3 +124,21 @@ def test_batch_errors(cg):
     with pytest.raises(cg.ChebGameError) as e:
         cg.ChebBatch([])
     assert e.value.code == cg.EINVAL
+
+
+def test_batch_mixed_dimensions_and_fit_paths(cg):
+    """Groups of d = 2, 3, 4 and both control-fit paths (N_u < N samples and
+    fits, N_u >= N composes) in one batch; each game equals its own solve."""
+    games = [W.make_game(4, 5, seed=21, instance=0), W.make_game(2, 9, seed=21, instance=1, Nu=6),
+             W.make_game(3, 7, seed=21, instance=2, Nu=5), W.make_game(3, 7, seed=21, instance=3),
+             W.make_game(4, 6, seed=21, instance=4, per_player=True), W.make_game(2, 9, seed=21, instance=5, Nu=6)]
+    hs = [cg.ChebGame(g, cg.FP64) for g in games]
+    B = cg.ChebBatch(hs)
+    assert len(B.groups()) == 5
+    rc, steps, _ = B.solve(20)
+    assert rc == cg.OK and np.all(steps == 20)
+    for g, h in zip(games, hs):
+        single = cg.ChebGame(g, cg.FP64)
+        single.solve(20)
+        assert torch.equal(single.get_state()[0], h.get_state()[0]), (g.d, g.N, g.Nu)
+        assert torch.equal(single.get_state()[1], h.get_state()[1]), (g.d, g.N, g.Nu)
