@@ -188,9 +188,10 @@ struct cg_game {
 namespace cg {
 void default_tiles(int d, int precision, int &rb, int &ocb)
 {
-    // measured on the d = 3, N = 32 game: FP64 fastest at (2, 2), FP32_CORR at (1, 2)
-    rb = precision == CG_FP32_CORR ? 1 : 2;
-    ocb = d >= 3 ? 2 : 1;
+    // measured: d = 3, N = 32: FP64 fastest at (2, 2), FP32_CORR at (1, 2);
+    // d = 4, N = 24: FP64 at (1, 1), FP32_CORR at (1, 2)
+    rb = (precision == CG_FP32_CORR || d == 4) ? 1 : 2;
+    ocb = d >= 3 && !(d == 4 && precision != CG_FP32_CORR) ? 2 : 1;
 }
 const GameConst &game_consts(const cg_game *g) { return g->hc; }
 const InstPtrs &game_inst(const cg_game *g) { return g->inst; }
