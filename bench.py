@@ -175,18 +175,21 @@ def run_batch(cg, W, torch, steps: int, warmup: int, count: int = 256, time_step
             "instances_rel_V_above_1e-8": int(np.sum(np.array(errs) > 1e-8))}
 
 
-def run_warm(cg, W, torch, n_train: int = 128, n_test: int = 16, N: int = 24, train_tol: float = 1e-7,
-             tol: float = 1e-8, max_steps: int = 40000):
+def run_warm(cg, W, torch, n_train: int = 4096, n_test: int = 16, N: int = 24, train_tol: float = 1e-7,
+             tol: float = 1e-8, max_steps: int = 40000, train_N: int = 12, train_steps: int = 40000):
     """Learned warm start on d=3 games (seed 5): the network is trained on
     `n_train` games solved by the method (batched, FP32 MFMA + FP64
-    correction, to residual `train_tol`), then `n_test` held-out games are
+    correction, to residual `train_tol`) on a train_N grid (the network takes
+    node coordinates, so it is then evaluated at the held-out games' N-grid
+    nodes), then `n_test` held-out games are
     solved to residual `tol` (a) plainly: FP64, one at a time, from zero, and
     (b) in the chosen form: FP32 MFMA + FP64 correction, batched, from the
     network's start, with the plain zero start as fallback for any game that
     does not converge."""
     import numpy as np
     log = lambda *a: print("bench:", *a, file=sys.stderr, flush=True)
-    train = [W.make_game(3, N, seed=5, instance=i) for i in range(n_train)]
+    # the network takes node coordinates, so its training games may use a coarser grid
+    train = [W.make_game(3, train_N or N, seed=5, instance=i) for i in range(n_train)]
     test = [W.make_game(3, N, seed=5, instance=100000 + i) for i in range(n_test)]
     t0 = time.perf_counter()
     hs = [cg.ChebGame(g, cg.FP32_CORR) for g in train]
@@ -211,12 +214,13 @@ def run_warm(cg, W, torch, n_train: int = 128, n_test: int = 16, N: int = 24, tr
     X, T = torch.cat(Xs), torch.cat(Ts)
     net = cg.MLP(W.mlp_init(seed=1), batch=8192)
     t0 = time.perf_counter()
-    l0 = net.train(X, T, steps=4000, lr=1e-3, seed=2)
-    net.train(X, T, steps=3000, lr=3e-4, seed=3)
-    l1 = net.train(X, T, steps=3000, lr=1e-4, seed=4)
+    s1, s2 = int(0.4 * train_steps), int(0.3 * train_steps)
+    l0 = net.train(X, T, steps=s1, lr=1e-3, seed=2)
+    net.train(X, T, steps=s2, lr=3e-4, seed=3)
+    l1 = net.train(X, T, steps=train_steps - s1 - s2, lr=1e-4, seed=4)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
-    log(f"trained 10000 Adam steps in {t_train:.1f} s")
+    log(f"trained {train_steps} Adam steps in {t_train:.1f} s")
     # (a) plain: FP64, one at a time, from zero
     plain_it, plain_ok, Vref = [], [], []
     t0 = time.perf_counter()
@@ -260,8 +264,9 @@ def run_warm(cg, W, torch, n_train: int = 128, n_test: int = 16, N: int = 24, tr
     both = [k for k in range(n_test) if plain_ok[k] and np.isfinite(wres[k]) and wres[k] < tol]
     pi = np.array([plain_it[k] for k in both])
     wi = np.array([wsteps[k] for k in both])
-    return {"workload": f"learned warm start, d=3 N={N} (seed 5): {n_train} training games, {n_test} held-out",
-            "train_games_converged": int(good.sum()), "train_samples": int(X.shape[0]),
+    return {"workload": f"learned warm start, d=3 N={N} (seed 5): {n_train} training games at N={train_N or N}, "
+                        f"{n_test} held-out",
+            "train_games_converged": int(good.sum()), "train_samples": int(X.shape[0]), "train_steps": train_steps,
             "data_generation_s": t_data, "training_s": t_train,
             "train_loss_first": float(l0[:10].mean().item()), "train_loss_last": float(l1[-100:].mean().item()),
             "tol": tol, "held_out_converged_both": len(both),
@@ -396,6 +401,9 @@ def main():
     ap.add_argument("--workload", default="c2",
                     choices=["c2", "c3", "batch", "warm", "eval", "sim", "accuracy"])
     ap.add_argument("--cpu-steps", type=int, default=6, help="oracle iterations timed for the CPU baseline")
+    ap.add_argument("--warm-train", type=int, default=4096, help="training games of the warm workload")
+    ap.add_argument("--warm-train-n", type=int, default=12, help="their nodes per dimension (0: same as held-out)")
+    ap.add_argument("--warm-steps", type=int, default=40000, help="Adam steps of the warm-start training")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for scaling rocprof byte counters)")
     args = ap.parse_args()
@@ -424,7 +432,8 @@ def main():
         print(json.dumps(run_eval(cg, W, torch, args.steps, args.warmup)), flush=True)
         return
     if args.workload == "warm":
-        print(json.dumps(run_warm(cg, W, torch)), flush=True)
+        print(json.dumps(run_warm(cg, W, torch, n_train=args.warm_train, train_N=args.warm_train_n,
+                                  train_steps=args.warm_steps)), flush=True)
         return
     if args.workload == "c3":
         g = W.config_game("C3")
