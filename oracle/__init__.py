@@ -38,6 +38,11 @@ class _Game(C.Structure):
                 ("beta", C.c_double * MAXD), ("A", C.c_double * MAXD), ("phi", C.c_double * MAXD)]
 
 
+class _Gen(C.Structure):
+    _fields_ = [("d", C.c_int), ("Np", C.c_int * MAXD), ("Nu", C.c_int * MAXD),
+                ("h", C.c_double), ("rho", C.c_double), ("pmax", C.c_double), ("umax", C.c_double)]
+
+
 def build(force: bool = True) -> str:
     """Compile oracle.c into liboracle.so (gcc, -O2, no FMA contraction, OpenMP)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
@@ -78,6 +83,10 @@ def lib() -> C.CDLL:
         L.or_step_sample.argtypes = [C.POINTER(_Game), _dp, _dp, C.c_long, _ip, _lp, _dp, _dp]
         L.or_solve.argtypes = [C.POINTER(_Game), _dp, _dp, C.c_int, C.c_double, _dp]
         L.or_solve.restype = C.c_int
+        L.or_gen_step.argtypes = [C.POINTER(_Gen), _dp, _dp, _dp, _dp, _dp, _dp]
+        L.or_gen_step.restype = C.c_double
+        L.or_gen_step_sample.argtypes = [C.POINTER(_Gen), _dp, _dp, _dp, _dp, C.c_long, _lp, _dp, _dp]
+        L.or_gen_step_sample.restype = None
         _lib = L
     return _lib
 
@@ -223,3 +232,68 @@ def simulate(g, U, p0, steps: int):
     ctrl = np.empty((max(steps, 1), g.d))
     lib().or_simulate(C.byref(_game(g)), _d(U), _d(p0), steps, _d(paths), _d(ctrl))
     return paths, ctrl[:steps]
+
+
+# ---- the generalised algorithm (non-separable controls, anisotropic grids) ----
+
+def _gen(gg) -> _Gen:
+    G = _Gen()
+    G.d = gg.d
+    for l in range(gg.d):
+        G.Np[l], G.Nu[l] = gg.n_p[l], gg.n_u[l]
+    G.h, G.rho, G.pmax, G.umax = gg.h, gg.rho, gg.p_max, gg.u_max
+    return G
+
+
+def gen_grids(gg):
+    """Physical state nodes per dimension and control nodes per player
+    (Lobatto nodes of Section 3.1 mapped to [0, P_M] and [0, U_M])."""
+    pn = [0.5 * gg.p_max * (nodes(n) + 1.0) for n in gg.n_p]
+    un = [0.5 * gg.u_max * (nodes(n) + 1.0) for n in gg.n_u]
+    return pn, un
+
+
+def gen_values(gg):
+    """Drift and payoff of the game on the oracle's own grid: [d][N_P][U_P] each."""
+    pn, un = gen_grids(gg)
+    return gg.values(pn, un)
+
+
+def gen_start(gg):
+    """V^{[0]} = 0 and u^{[0]} = u_init (default U_M / 2), each [d][N_P]."""
+    u0 = gg.u_init if gg.u_init is not None else np.full(gg.d, 0.5 * gg.u_max)
+    V = np.zeros((gg.d, gg.n_nodes))
+    U = np.repeat(np.asarray(u0, dtype=np.float64)[:, None], gg.n_nodes, axis=1)
+    return V, U
+
+
+def gen_step(gg, gvals, pvals, V, U):
+    """One iteration of the generalised algorithm; returns (Vn, Un, residual)."""
+    gv, pv, V, U = _f64(gvals), _f64(pvals), _f64(V), _f64(U)
+    Vn, Un = np.empty_like(V), np.empty_like(U)
+    r = lib().or_gen_step(C.byref(_gen(gg)), _d(gv), _d(pv), _d(V), _d(U), _d(Vn), _d(Un))
+    return Vn, Un, r
+
+
+def gen_step_sample(gg, gvals, pvals, V, U, nodes_):
+    """Updates of every player at the listed nodes; returns (Vn, Un), [d][count]."""
+    gv, pv, V, U = _f64(gvals), _f64(pvals), _f64(V), _f64(U)
+    nd = np.ascontiguousarray(nodes_, dtype=np.int64)
+    Vn, Un = np.empty((gg.d, nd.size)), np.empty((gg.d, nd.size))
+    lib().or_gen_step_sample(C.byref(_gen(gg)), _d(gv), _d(pv), _d(V), _d(U), nd.size,
+                             nd.ctypes.data_as(_lp), _d(Vn), _d(Un))
+    return Vn, Un
+
+
+def gen_solve(gg, gvals, pvals, steps: int, tol: float = 0.0, V=None, U=None):
+    """Iterate from (V, U) (default gen_start); returns (V, U, residuals)."""
+    if V is None:
+        V, U = gen_start(gg)
+    V, U = _f64(V).copy(), _f64(U).copy()
+    res = []
+    for _ in range(steps):
+        V, U, r = gen_step(gg, gvals, pvals, V, U)
+        res.append(r)
+        if tol > 0.0 and r < tol:
+            break
+    return V, U, np.asarray(res)

@@ -437,3 +437,136 @@ void or_simulate(const or_game *g, const double *U, const double *p0, int n_step
     free(work);
     free(coef);
 }
+
+/* ---------------------------------------------------------------------- */
+/* The generalised algorithm of Section 2.1 (the form the paper gives for  */
+/* dynamics that are not separable in the controls), with anisotropic     */
+/* grids N_p, N_u (Step 0) and node-wise control polynomials g^i_p(u)     */
+/* (Section 3.3; Step 0 of Section 3.4).                                   */
+
+typedef struct {
+    int d;
+    int Np[OR_MAXD];   /* Lobatto nodes of each state dimension */
+    int Nu[OR_MAXD];   /* control nodes of each player on [0, U_M] */
+    double h, rho, pmax, umax;
+} or_gen;
+
+/* Update of every player at state node j (Steps 1-4 of the generalised
+ * algorithm).  gvals[k][j][.] and pvals[i][j][.] hold, on the tensor grid of
+ * control nodes (shape Nu, C order), the drift component k and the payoff
+ * of player i at node j.  For each player i:
+ *   - Step 0, done here per node: the control polynomials interpolate those
+ *     values (Algorithm Cnv over the control modes);
+ *   - Step 1: along the line u -> [u, u^{[r]}_{-i}(p_j)] they give the drift
+ *     vector and the payoff, evaluated at the control nodes u_m of player i
+ *     (the n-d series at the full control vector);
+ *   - Step 2: the samples are h G_i + delta_h V_i^{[r]}(p_j + h g(u_m))
+ *     (Reading: the Bellman form of Section 2.1 with the payoff, as in the
+ *     separable case);
+ *   - Steps 3-4: the samples are fitted in u by eq. (forcoef), the new
+ *     control is the global argmax of the fit on [0, U_M] and the new value
+ *     the fit there.
+ * coefV holds the coefficient tensors of V^{[r]} ([d][N_P]), U the controls
+ * u^{[r]} ([d][N_P]); vn, un receive the d new values and controls of node
+ * j.  'ctl' holds 2 d prod(Nu) doubles, 'work' max(prod(Np), prod(Nu)). */
+static void gen_node(const or_gen *g, long j, const double *gvals, const double *pvals,
+                     const double *coefV, const double *U, double xn[][OR_MAXN],
+                     double un[][OR_MAXN], double *vn, double *un_out, double *ctl, double *work)
+{
+    int d = g->d;
+    long NP = 1, UP = 1;
+    for (int l = 0; l < d; ++l) { NP *= g->Np[l]; UP *= g->Nu[l]; }
+    double p[OR_MAXD], ubar[OR_MAXD], u[OR_MAXD], yv[OR_MAXD], x[OR_MAXD], gd[OR_MAXD];
+    double vals[OR_MAXN], q[OR_MAXN];
+    long rem = j;
+    for (int l = d - 1; l >= 0; --l) {
+        int k = (int)(rem % g->Np[l]);
+        rem /= g->Np[l];
+        p[l] = 0.5 * g->pmax * (xn[l][k] + 1.0); /* node mapped to [0, P_M] (Section 3.4) */
+    }
+    for (int l = 0; l < d; ++l) ubar[l] = U[l * NP + j];
+    /* Step 0 for this node: drift components 0..d-1, then the payoffs */
+    for (int k = 0; k < d; ++k) {
+        or_transform(d, g->Nu, NULL, gvals + ((long)k * NP + j) * UP, ctl + (long)k * UP);
+        or_transform(d, g->Nu, NULL, pvals + ((long)k * NP + j) * UP, ctl + (long)(d + k) * UP);
+    }
+    double delta = 1.0 - g->rho * g->h;
+    for (int i = 0; i < d; ++i) {
+        int nu = g->Nu[i];
+        for (int m = 0; m < nu; ++m) {
+            for (int l = 0; l < d; ++l) u[l] = ubar[l];
+            u[i] = un[i][m];
+            for (int l = 0; l < d; ++l) yv[l] = 2.0 * u[l] / g->umax - 1.0;
+            for (int k = 0; k < d; ++k) gd[k] = or_eval_point(d, g->Nu, ctl + (long)k * UP, yv, work);
+            double G = or_eval_point(d, g->Nu, ctl + (long)(d + i) * UP, yv, work);
+            for (int l = 0; l < d; ++l) x[l] = 2.0 * (p[l] + g->h * gd[l]) / g->pmax - 1.0;
+            double cont = or_eval_point(d, g->Np, coefV + (long)i * NP, x, work);
+            vals[m] = g->h * G + delta * cont;
+        }
+        or_coef_1d(nu, vals, 1, q, 1);
+        double s;
+        vn[i] = or_argmax_line(nu, q, &s, NULL);
+        un_out[i] = 0.5 * g->umax * (s + 1.0);
+    }
+}
+
+/* Update of the listed nodes (every node when nodes == NULL, count = N_P).
+ * V, U are [d][N_P]; Vn, Un receive [d][count].  Returns the largest
+ * |Vn - V| over the listed nodes (the TOL test of Step 4 when all are). */
+static double gen_update(const or_gen *g, const double *gvals, const double *pvals, const double *V,
+                         const double *U, long count, const long *nodes, double *Vn, double *Un)
+{
+    int d = g->d;
+    long NP = 1, UP = 1;
+    for (int l = 0; l < d; ++l) { NP *= g->Np[l]; UP *= g->Nu[l]; }
+    double xn[OR_MAXD][OR_MAXN], un[OR_MAXD][OR_MAXN];
+    for (int l = 0; l < d; ++l) {
+        or_nodes(g->Np[l], xn[l]);
+        double su[OR_MAXN];
+        or_nodes(g->Nu[l], su);
+        for (int m = 0; m < g->Nu[l]; ++m) un[l][m] = 0.5 * g->umax * (su[m] + 1.0);
+    }
+    double *coefV = (double *)malloc(sizeof(double) * (size_t)(d * NP));
+    for (int i = 0; i < d; ++i) or_transform(d, g->Np, NULL, V + i * NP, coefV + i * NP);
+    long wsz = NP > UP ? NP : UP;
+    double res = 0.0;
+    #pragma omp parallel reduction(max:res)
+    {
+        double *ctl = (double *)malloc(sizeof(double) * (size_t)(2 * d * UP));
+        double *work = (double *)malloc(sizeof(double) * (size_t)wsz);
+        double vn[OR_MAXD], unn[OR_MAXD];
+        #pragma omp for schedule(dynamic, 4)
+        for (long t = 0; t < count; ++t) {
+            long j = nodes ? nodes[t] : t;
+            gen_node(g, j, gvals, pvals, coefV, U, xn, un, vn, unn, ctl, work);
+            for (int i = 0; i < d; ++i) {
+                Vn[(long)i * count + t] = vn[i];
+                Un[(long)i * count + t] = unn[i];
+                double e = fabs(vn[i] - V[(long)i * NP + j]);
+                if (!(e <= res)) res = e; /* a NaN wins */
+            }
+        }
+        free(work);
+        free(ctl);
+    }
+    free(coefV);
+    return res;
+}
+
+/* One iteration of the generalised algorithm on every node: V, U, Vn, Un
+ * are [d][N_P]; gvals, pvals [d][N_P][prod(Nu)].  Returns max |Vn - V|. */
+double or_gen_step(const or_gen *g, const double *gvals, const double *pvals, const double *V,
+                   const double *U, double *Vn, double *Un)
+{
+    long NP = 1;
+    for (int l = 0; l < g->d; ++l) NP *= g->Np[l];
+    return gen_update(g, gvals, pvals, V, U, NP, NULL, Vn, Un);
+}
+
+/* The same update at the listed nodes only (every player of each); Vn, Un
+ * receive [d][count].  Used to check large grids on sampled outputs. */
+void or_gen_step_sample(const or_gen *g, const double *gvals, const double *pvals, const double *V,
+                        const double *U, long count, const long *nodes, double *Vn, double *Un)
+{
+    gen_update(g, gvals, pvals, V, U, count, nodes, Vn, Un);
+}

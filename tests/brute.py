@@ -95,3 +95,66 @@ def step(game, V: np.ndarray, U: np.ndarray, grid: int = 20001):
             Un[i, j] = cands[best]
             Vn[i, j] = cv[best]
     return Vn, Un
+
+
+def _nodes(n: int) -> np.ndarray:
+    return np.cos(np.pi * np.arange(n) / (n - 1))
+
+
+def _evaluate_any(coef: np.ndarray, x: np.ndarray) -> np.ndarray:
+    """Series value at rows of x for any d, by chebval along the last mode
+    repeatedly (numpy's tensor=False evaluation of each point)."""
+    out = np.empty(x.shape[0])
+    for q in range(x.shape[0]):
+        c = coef
+        for m in range(coef.ndim - 1, -1, -1):
+            c = npc.chebval(x[q, m], np.moveaxis(c, m, 0)) if c.ndim > 1 else npc.chebval(x[q, m], c)
+        out[q] = float(c)
+    return out
+
+
+def general_step(gg, V: np.ndarray, U: np.ndarray, grid: int = 4001):
+    """One iteration of the general (non-separable) algorithm on every node.
+
+    The same approximations as the method (control polynomials interpolating
+    the drift and payoff on the control grid; the line function fitted at
+    the player's control nodes), each obtained differently: Vandermonde
+    solves for every interpolant, numpy's chebval for every series, and the
+    maximum of the fitted line polynomial by a dense grid plus golden-section
+    polishing."""
+    d = gg.d
+    n_p, n_u = tuple(gg.n_p), tuple(gg.n_u)
+    pn = [0.5 * gg.p_max * (_nodes(n) + 1.0) for n in n_p]
+    un = [0.5 * gg.u_max * (_nodes(n) + 1.0) for n in n_u]
+    gvals, pvals = gg.values(pn, un)
+    delta = 1.0 - gg.rho * gg.h
+    NP = int(np.prod(n_p))
+    coefs = [coefficients(V[i].reshape(n_p)) for i in range(d)]
+    idx = np.indices(n_p).reshape(d, -1).T
+    sg = np.linspace(-1.0, 1.0, grid)
+    Vn, Un = np.empty((d, NP)), np.empty((d, NP))
+    for j, kk in enumerate(idx):
+        p = np.array([pn[l][kk[l]] for l in range(d)])
+        gc = [coefficients(gvals[k, j].reshape(n_u)) for k in range(d)]
+        pc = [coefficients(pvals[i, j].reshape(n_u)) for i in range(d)]
+        for i in range(d):
+            nu = n_u[i]
+            Uc = np.repeat(U[:, j][None, :], nu, axis=0)
+            Uc[:, i] = un[i]
+            y = 2.0 * Uc / gg.u_max - 1.0
+            drift = np.stack([_evaluate_any(gc[k], y) for k in range(d)], axis=1)
+            G = _evaluate_any(pc[i], y)
+            x = 2.0 * (p[None, :] + gg.h * drift) / gg.p_max - 1.0
+            samples = gg.h * G + delta * _evaluate_any(coefs[i], x)
+            q = np.linalg.solve(npc.chebvander(_nodes(nu), nu - 1), samples)
+            f = lambda s: float(npc.chebval(s, q))
+            vals = npc.chebval(sg, q)
+            k = int(np.argmax(vals))
+            lo, hi = sg[max(k - 1, 0)], sg[min(k + 1, grid - 1)]
+            s_star = _golden_max(f, lo, hi)
+            cands = np.array([lo, s_star, hi])
+            cv = npc.chebval(cands, q)
+            b = int(np.argmax(cv))
+            Vn[i, j] = cv[b]
+            Un[i, j] = 0.5 * gg.u_max * (cands[b] + 1.0)
+    return Vn, Un

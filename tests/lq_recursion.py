@@ -41,14 +41,25 @@ class LQState:
 
 def lq_iterate(game, steps: int):
     """Yield the LQState after each of ``steps`` iterations from V = 0, u = A."""
-    d = game.d
     K = np.asarray(game.K, dtype=np.float64)
     m = np.asarray(game.m, dtype=np.float64)
     M = K / m[:, None] - np.diag(game.c)
-    h, delta = game.h, 1.0 - game.rho * game.h
+    B = np.diag(np.asarray(game.beta, dtype=np.float64))
+    yield from lq_iterate_mats(M, B, game.A, game.phi, game.h, game.rho, game.A, steps)
+
+
+def lq_iterate_mats(M, B, A, phi, h: float, rho: float, a0, steps: int):
+    """The same recursion for the drift g = M p + B u with a full emission
+    matrix B (column l: how player l's emissions enter every stock), which
+    makes the game non-separable in the controls: the frozen controls of the
+    other players shift every component of the update point.  Starts from
+    V = 0 and the constant controls a0."""
+    M, B = np.asarray(M, dtype=np.float64), np.asarray(B, dtype=np.float64)
+    d = M.shape[0]
+    delta = 1.0 - rho * h
     I = np.eye(d)
     st = LQState(d)
-    st.a = np.asarray(game.A, dtype=np.float64).copy()
+    st.a = np.asarray(a0, dtype=np.float64).copy()
     for _ in range(steps):
         nx = LQState(d)
         for i in range(d):
@@ -56,18 +67,18 @@ def lq_iterate(game, steps: int):
             e0 = np.zeros(d)
             for l in range(d):
                 if l != i:
-                    E = E + h * game.beta[l] * np.outer(I[l], st.f[l])
-                    e0 = e0 + h * game.beta[l] * st.a[l] * I[l]
-            b = h * game.beta[i] * I[i]
+                    E = E + h * np.outer(B[:, l], st.f[l])
+                    e0 = e0 + h * st.a[l] * B[:, l]
+            b = h * B[:, i]
             Qi, qi, si = st.Q[i], st.q[i], st.s[i]
             den = h - delta * b @ Qi @ b
             fi = delta * (E.T @ Qi @ b) / den
-            ai = (h * game.A[i] + delta * b @ (Qi @ e0 + qi)) / den
+            ai = (h * A[i] + delta * b @ (Qi @ e0 + qi)) / den
             F = E + np.outer(b, fi)
             gv = e0 + b * ai
-            nx.Q[i] = h * (-np.outer(fi, fi) - game.phi[i] * np.outer(I[i], I[i])) + delta * F.T @ Qi @ F
-            nx.q[i] = h * (game.A[i] - ai) * fi + delta * (F.T @ Qi @ gv + F.T @ qi)
-            nx.s[i] = h * (game.A[i] * ai - 0.5 * ai * ai) + delta * (0.5 * gv @ Qi @ gv + qi @ gv + si)
+            nx.Q[i] = h * (-np.outer(fi, fi) - phi[i] * np.outer(I[i], I[i])) + delta * F.T @ Qi @ F
+            nx.q[i] = h * (A[i] - ai) * fi + delta * (F.T @ Qi @ gv + F.T @ qi)
+            nx.s[i] = h * (A[i] * ai - 0.5 * ai * ai) + delta * (0.5 * gv @ Qi @ gv + qi @ gv + si)
             nx.a[i], nx.f[i] = ai, fi
         st = nx
         yield st
@@ -91,3 +102,10 @@ def lq_nodal(game, steps: int):
     V = np.stack([st.value(i, P) for i in range(game.d)])
     U = np.stack([st.control(i, P) for i in range(game.d)])
     return V, U
+
+
+def node_points_aniso(n_p, p_max: float) -> np.ndarray:
+    """Physical node coordinates of an anisotropic grid (prod(n_p) x d), C order."""
+    p1 = [0.5 * p_max * (np.cos(np.pi * np.arange(n) / (n - 1)) + 1.0) for n in n_p]
+    grids = np.meshgrid(*p1, indexing="ij")
+    return np.stack([g.ravel() for g in grids], axis=1)

@@ -219,3 +219,119 @@ def theta_features(game) -> np.ndarray:
     th = np.asarray(game.theta, dtype=np.float64)
     nom = np.array([NOMINAL[k] for k in THETA_ORDER])
     return (th / nom - 1.0).astype(np.float32)
+
+
+# ---- general (non-separable, anisotropic) games ----
+#
+# The general form of the method takes the drift g(p, u) and the payoffs
+# G_i(p, u) as functions of the whole control vector.  A game of that form is
+# described here by its parameters and by two functions of coordinates; the
+# caller evaluates them at the grid the solver defines (node coordinates are
+# an input of `GeneralGame.values`, never computed here).
+
+@dataclass
+class GeneralGame:
+    """A d-player pollution game with dynamics and payoffs that need not be
+    separable in the controls.
+
+    drift     g_k(p, u) = (M p)_k + sum_l B_kl u_l - eta_k p_k u_k
+    payoff    G_i(p, u) = b_i(u_i) - phi_i p_i^2 / 2 - kappa_i u_i mean_{l != i} u_l
+              with b_i(u) = A_i log(1 + u) ("log") or u (A_i - u / 2) ("quadratic")
+
+    B's off-diagonal entries carry emissions across borders, eta couples the
+    stock to the emission factor, kappa is a competition term; with B
+    diagonal, eta = kappa = 0 and the quadratic benefit this is the LQ game.
+    """
+    d: int
+    n_p: tuple                  # Lobatto nodes per state dimension
+    n_u: tuple                  # control nodes per player
+    h: float
+    rho: float
+    p_max: float
+    u_max: float
+    M: np.ndarray               # (d, d)
+    B: np.ndarray               # (d, d)
+    eta: np.ndarray             # (d,)
+    A: np.ndarray
+    phi: np.ndarray
+    kappa: np.ndarray
+    benefit: str = "log"
+    u_init: Optional[np.ndarray] = None   # u^{[0]} per player (default u_max / 2)
+
+    @property
+    def n_nodes(self) -> int:
+        return int(np.prod(self.n_p))
+
+    @property
+    def n_ctl(self) -> int:
+        return int(np.prod(self.n_u))
+
+    def drift(self, P: np.ndarray, Uc: np.ndarray) -> np.ndarray:
+        """g(P, Uc) for broadcastable P[..., d], Uc[..., d]; returns [d, ...]."""
+        P, Uc = np.broadcast_arrays(P, Uc)
+        out = np.einsum("kl,...l->k...", self.M, P) + np.einsum("kl,...l->k...", self.B, Uc)
+        return out - self.eta.reshape((-1,) + (1,) * (P.ndim - 1)) * np.moveaxis(P * Uc, -1, 0)
+
+    def payoff(self, P: np.ndarray, Uc: np.ndarray) -> np.ndarray:
+        """G(P, Uc) for every player; returns [d, ...]."""
+        P, Uc = np.broadcast_arrays(P, Uc)
+        Pm, Um = np.moveaxis(P, -1, 0), np.moveaxis(Uc, -1, 0)
+        sh = (-1,) + (1,) * (P.ndim - 1)
+        A, phi, kap = self.A.reshape(sh), self.phi.reshape(sh), self.kappa.reshape(sh)
+        if self.benefit == "log":
+            ben = A * np.log1p(Um)
+        else:
+            ben = Um * (A - 0.5 * Um)
+        others = (Um.sum(axis=0, keepdims=True) - Um) / max(self.d - 1, 1)
+        return ben - 0.5 * phi * Pm * Pm - kap * Um * others
+
+    def values(self, pnodes, unodes):
+        """Drift and payoff on the grid: [d][N_P][U_P] each, node index and
+        control index in C order over the coordinate lists given per state
+        dimension (physical, pnodes[l]) and per player (unodes[i])."""
+        P = np.stack(np.meshgrid(*pnodes, indexing="ij"), axis=-1).reshape(-1, self.d)
+        Uc = np.stack(np.meshgrid(*unodes, indexing="ij"), axis=-1).reshape(-1, self.d)
+        g = self.drift(P[:, None, :], Uc[None, :, :])
+        G = self.payoff(P[:, None, :], Uc[None, :, :])
+        return np.ascontiguousarray(g), np.ascontiguousarray(G)
+
+
+def general_game(d: int, n_p, n_u, seed: int, instance: int = 0, *, h: float = 1e-2,
+                 spill: float = 0.3, benefit: str = "log") -> GeneralGame:
+    """Seeded non-separable game: the per-player parameters of `make_game`
+    (per_player=True) plus cross-border emission shares B_kl = spill beta_l
+    w_kl (w ~ U[0,1)), stock-emission coupling eta_k ~ 0.5 U[0,1) and
+    competition kappa_i ~ 0.3 (0.5 + U[0,1))."""
+    base = make_game(d, 3, seed, instance, h=h, per_player=True)
+    M = base.K / base.m[:, None] - np.diag(base.c)
+    w = uniform(seed, 3000 + instance, np.arange(d * d + 2 * d, dtype=np.uint64))
+    B = spill * base.beta[None, :] * w[:d * d].reshape(d, d)
+    np.fill_diagonal(B, base.beta)
+    eta = 0.5 * w[d * d:d * d + d]
+    kappa = 0.3 * (0.5 + w[d * d + d:])
+    return GeneralGame(d, tuple(int(x) for x in n_p), tuple(int(x) for x in n_u), h, base.rho,
+                       base.p_max, base.u_max, M, B, eta, base.A.copy(), base.phi.copy(), kappa, benefit)
+
+
+def general_from_lq(game: Game, n_p=None, n_u=None) -> GeneralGame:
+    """The LQ game written in the general form (B = diag(beta), eta = kappa = 0)."""
+    d = game.d
+    M = np.asarray(game.K, dtype=np.float64) / np.asarray(game.m)[:, None] - np.diag(game.c)
+    n_p = tuple(n_p) if n_p is not None else (game.N,) * d
+    n_u = tuple(n_u) if n_u is not None else (game.n_u,) * d
+    return GeneralGame(d, n_p, n_u, game.h, game.rho, game.p_max, game.u_max, M,
+                       np.diag(np.asarray(game.beta, dtype=np.float64)), np.zeros(d),
+                       np.asarray(game.A, dtype=np.float64), np.asarray(game.phi, dtype=np.float64),
+                       np.zeros(d), "quadratic", np.asarray(game.A, dtype=np.float64).copy())
+
+
+def general_state(gg: GeneralGame, pnodes, seed: int, stream: int = 91):
+    """Seeded smooth start (V, U), each [d][N_P], at the given node
+    coordinates: V_i(p) = -sum_l a_il (p_l/P_M)^2 + 0.2 sum_l sin(w_il p_l/P_M + s_il),
+    u_i(p) = U_M (0.5 + 0.3 sin(sum_l v_il p_l / P_M))."""
+    d = gg.d
+    r = uniform(seed, stream, np.arange(5 * d * d, dtype=np.uint64)).reshape(5, d, d)
+    P = np.stack(np.meshgrid(*pnodes, indexing="ij"), axis=-1).reshape(-1, d) / gg.p_max
+    V = -(P * P) @ (0.5 + r[0]).T + 0.2 * np.sin(P[:, None, :] * (1.0 + 2.0 * r[1])[None] + 6.0 * r[2][None]).sum(-1)
+    U = gg.u_max * (0.5 + 0.3 * np.sin(P @ (2.0 * r[3] - 1.0).T * 3.0))
+    return np.ascontiguousarray(V.T), np.ascontiguousarray(U.T)
