@@ -390,6 +390,73 @@ def run_accuracy(cg, W, torch):
             "hjb_residual_of_reference": hjb, "rows": rows}
 
 
+def run_general(cg, W, torch, steps: int, warmup: int, iters: int = 50, cpu: bool = True):
+    """General form (non-separable drift and payoff, anisotropic grids): d=3,
+    n_p = (32, 24, 16) state nodes (12288), n_u = (8, 8, 8) control nodes,
+    seed-6 game from its seeded smooth start; a step is `iters` iterations.
+    Dominant kernel: the evaluation of V at the N_P sum(n_u) update points
+    (all players in one launch), 2 N_P flops per point."""
+    import numpy as np
+    import oracle
+    gg = W.general_game(3, (32, 24, 16), (8, 8, 8), seed=6)
+    G = cg.ChebGeneral.from_game(gg)
+    pn, _ = cg.general_nodes(gg)
+    V0, U0 = W.general_state(gg, pn, seed=6)
+    V0t, U0t = torch.from_numpy(V0).cuda(), torch.from_numpy(U0).cuda()
+    NP = gg.n_nodes
+    npts = NP * sum(gg.n_u)
+    # parity: one iteration from the seeded start, sampled nodes vs the oracle
+    G.set_state(V0t, U0t)
+    G.step(1)
+    Vg, Ug, _ = G.get_state()
+    rng = np.arange(0, NP, NP // 256)
+    po, _ = oracle.gen_grids(gg)
+    V0o, U0o = W.general_state(gg, po, seed=6)
+    gv, pv = oracle.gen_values(gg)
+    Vs, Us = oracle.gen_step_sample(gg, gv, pv, V0o, U0o, rng)
+    err_v = float(np.max(np.abs(Vg.cpu().numpy()[:, rng] - Vs)) / np.max(np.abs(Vs)))
+    err_u = float(np.max(np.abs(Ug.cpu().numpy()[:, rng] - Us)))
+    for _ in range(warmup):
+        G.set_state(V0t, U0t)
+        G.step(iters)
+    torch.cuda.synchronize()
+    G.set_state(V0t, U0t)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        G.step(iters, sync=False)
+    G.step(0)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_it = dt * 1e3 / (steps * iters)
+    G.set_state(V0t, U0t)
+    G.profile(True)
+    G.step(iters)
+    ph, n = G.profile(False)
+    ph = [x / n for x in ph]
+    flops = 2.0 * NP * npts
+    ach = flops / (ph[2] * 1e-3) / 1e12
+    out = {"workload": "general-form pollution game d=3 (non-separable drift and payoff), n_p=(32,24,16) "
+                       "state nodes, n_u=(8,8,8) control nodes, seed 6, seeded smooth start",
+           "iterations_per_s": 1e3 / ms_it, "ms_per_iteration": ms_it, "steps": steps, "iters_per_step": iters,
+           "update_points_per_iteration": npts,
+           "phase_ms_per_iteration": {"transform": ph[0], "points": ph[1], "evaluation": ph[2], "line": ph[3]},
+           "roofline": {"bound": "mfma", "kernel": "evaluation of V at the update points (FP64 MFMA)",
+                        "achieved": ach, "peak": PEAK["fp64"], "unit": "TFLOP/s", "frac": ach / PEAK["fp64"],
+                        "traffic": None},
+           "err_vs_oracle_one_iteration_256_nodes": {"V_rel": err_v, "U_abs": err_u}}
+    if cpu:
+        sample = np.arange(NP)
+        t0 = time.perf_counter()
+        oracle.gen_step_sample(gg, gv, pv, V0o, U0o, sample)
+        dtc = time.perf_counter() - t0
+        per_it = dtc * NP / sample.size
+        out["cpu_baseline"] = {"value": 1.0 / per_it, "unit": "iterations/s", "cores": oracle.num_threads(),
+                               "kind": "oracle", "sample": f"one full iteration ({sample.size} nodes, "
+                                                           f"every player; {dtc:.1f} s)"}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -399,7 +466,7 @@ def main():
                     help="path reported as value; the other is timed beside it")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="c2",
-                    choices=["c2", "c3", "batch", "warm", "eval", "sim", "accuracy"])
+                    choices=["c2", "c3", "batch", "warm", "eval", "sim", "accuracy", "general"])
     ap.add_argument("--cpu-steps", type=int, default=6, help="oracle iterations timed for the CPU baseline")
     ap.add_argument("--warm-train", type=int, default=4096, help="training games of the warm workload")
     ap.add_argument("--warm-train-n", type=int, default=12, help="their nodes per dimension (0: same as held-out)")
@@ -430,6 +497,10 @@ def main():
         return
     if args.workload == "eval":
         print(json.dumps(run_eval(cg, W, torch, args.steps, args.warmup)), flush=True)
+        return
+    if args.workload == "general":
+        print(json.dumps(run_general(cg, W, torch, args.steps, args.warmup, cpu=not args.no_cpu_baseline)),
+              flush=True)
         return
     if args.workload == "warm":
         print(json.dumps(run_warm(cg, W, torch, n_train=args.warm_train, train_N=args.warm_train_n,

@@ -294,6 +294,107 @@ int cg_profile(cg_game *game, int enable, double *kernel_ms, int64_t *launches);
  * FP64.  CG_EINVAL for other values. */
 int cg_set_tiles(cg_game *game, int32_t rb, int32_t ocb);
 
+/* ------------------------------------------------------------------------
+ * General form (Section 2.1's algorithm for dynamics that are not separable
+ * in the controls, with the node-wise control polynomials of Section 3.3 and
+ * the offline Step 0 of Section 3.4).
+ *
+ * The game is given by samples instead of a formula:
+ *   drift   g_k(p, u), k = 0..d-1   (dp/dt = g(p, u))
+ *   payoff  G_i(p, u), i = 0..d-1
+ * at every state node p_j of an anisotropic Lobatto grid (n_nodes[l] nodes
+ * along state dimension l) and every control node u of the tensor grid of
+ * control nodes (n_unodes[i] nodes for player i).  Step 0 interpolates them
+ * in u (one control polynomial per node, component and payoff; Algorithm
+ * Cnv).  Each iteration, for every player i and node p_j:
+ *   Step 1  the control polynomials are evaluated along the line
+ *           u -> [u, u^{[r]}_{-i}(p_j)] at player i's control nodes u_m;
+ *   Step 2  V_i^{[r]} is evaluated at the update points p_j + h g(p_j, .)
+ *           (a full d-dimensional evaluation per control node) and the
+ *           samples h G_i + (1 - rho h) V_i^{[r]} are formed;
+ *   Step 3  the samples are fitted in u (eq. (forcoef)) and the fit's
+ *           maximiser over [0, u_max] is the new control;
+ *   Step 4  the fit there is the new value; residual max |V^{[r+1]} - V^{[r]}|.
+ * All players use u^{[r]} (simultaneous update).
+ *
+ * Grids: state node k of dimension l is p = p_max (x_k + 1) / 2 with
+ * x_k = cos(pi k / (n_nodes[l] - 1)); control node m of player i is
+ * u = u_max (cos(pi m / (n_unodes[i] - 1)) + 1) / 2 (index 0 = u_max).
+ * N_P = prod n_nodes, U_P = prod n_unodes; node and control indices run in C
+ * order over their grids (last dimension fastest).  State arrays are
+ * [d][N_P].
+ * ---------------------------------------------------------------------- */
+#define CG_MAX_NU 16 /* control nodes per player in the general form */
+
+typedef struct cg_general_desc {
+    int32_t d;                      /* players = state dimension, 2..CG_MAX_D */
+    int32_t n_nodes[CG_MAX_D];      /* state nodes per dimension, 3..CG_MAX_N */
+    int32_t n_unodes[CG_MAX_D];     /* control nodes per player, 3..CG_MAX_NU */
+    double h;                       /* time step, > 0 */
+    double rho;                     /* discount rate; requires 0 < rho h < 1 */
+    double p_max;                   /* state box [0, p_max]^d, > 0 */
+    double u_max;                   /* control interval [0, u_max], > 0 */
+    double u_init[CG_MAX_D];        /* u^{[0]} of each player, in [0, u_max] (V^{[0]} = 0) */
+    const double *drift_dev;        /* device [d][N_P][U_P]: g_k(p_j, u_t) */
+    const double *payoff_dev;       /* device [d][N_P][U_P]: G_i(p_j, u_t) */
+} cg_general_desc;
+
+typedef struct cg_general cg_general;
+
+/* Grid coordinates of the description (host arrays): pnodes receives the
+ * physical state nodes of dimension 0, then 1, ... (sum n_nodes doubles);
+ * unodes the control nodes of player 0, 1, ... (sum n_unodes doubles).
+ * Either may be NULL.  The drift and payoff samples are taken there.
+ * Errors: CG_EINVAL, CG_EUNSUPPORTED (sizes outside the compiled set). */
+int cg_general_nodes(const cg_general_desc *desc, double *pnodes, double *unodes);
+
+/* Bytes of device workspace cg_general_init needs (0 if the description is
+ * invalid; cg_last_error says why).  It holds the control-polynomial
+ * coefficients (2 d N_P U_P doubles), the update points (d N_P sum n_unodes
+ * x (d + 2) doubles) and the state. */
+size_t cg_general_workspace_bytes(const cg_general_desc *desc);
+
+/* Step 0: validates the description, interpolates the drift and payoff
+ * samples into control polynomials (in the workspace), sets V^{[0]} = 0 and
+ * u^{[0]} = u_init.  The work runs on 'stream' and the call synchronises it,
+ * so drift_dev and payoff_dev may be released on return.  The workspace
+ * (>= cg_general_workspace_bytes, 256-byte aligned) must outlive the handle;
+ * later calls queue their work on the same stream.
+ * Errors: CG_EINVAL, CG_EUNSUPPORTED, CG_ENOMEM, CG_EDEVICE. */
+int cg_general_init(const cg_general_desc *desc, void *ws_dev, size_t ws_bytes, void *stream,
+                    cg_general **out);
+
+/* nsteps iterations (Steps 1-4 above).  If residual_out is not NULL the call
+ * synchronises the stream and stores the last residual; CG_ENONFINITE if a
+ * non-finite value appeared. */
+int cg_general_step(cg_general *game, int32_t nsteps, double *residual_out);
+
+/* Iterate until the residual is < tol (strict; tol <= 0: exactly max_steps
+ * iterations) or max_steps; synchronises.  Returns CG_OK, CG_ENOTCONVERGED
+ * or CG_ENONFINITE; *steps_done and *residual (nullable) as for cg_solve.
+ * The host checks the device-side test every 8 iterations; the iterations
+ * queued after convergence leave the state unchanged. */
+int cg_general_solve(cg_general *game, int32_t max_steps, double tol, int32_t *steps_done, double *residual);
+
+/* Copies of the current V and u ([d][N_P] each, device, nullable) and the
+ * iterations done since init (host, nullable; synchronises).  set_state
+ * replaces them (U_dev NULL keeps u).  Queued on the game's stream. */
+int cg_general_get_state(cg_general *game, double *V_dev, double *U_dev, int32_t *r);
+int cg_general_set_state(cg_general *game, const double *V_dev, const double *U_dev);
+
+/* Per-phase timing with HIP events on the game's stream.  With enable != 0
+ * every later iteration records events between its phases.  If phase_ms is
+ * not NULL the call synchronises and stores the summed milliseconds since the
+ * previous call of [0] the coefficient transform (and the packing of the
+ * coefficients for the evaluation), [1] Step 1 (control polynomials and
+ * update points), [2] Step 2 (the evaluation kernel of V, all players in one
+ * launch) and [3] Steps 3-4 (fit, argmax, residual); *steps the iterations
+ * timed. */
+int cg_general_profile(cg_general *game, int enable, double *phase_ms, int64_t *steps);
+
+/* Releases the handle (not the workspace).  NULL is accepted. */
+int cg_general_destroy(cg_general *game);
+
 #ifdef __cplusplus
 }
 #endif

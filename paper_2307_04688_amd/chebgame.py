@@ -36,6 +36,15 @@ class GameDesc(C.Structure):
                 ("beta", C.POINTER(C.c_double)), ("A", C.POINTER(C.c_double)), ("phi", C.POINTER(C.c_double))]
 
 
+MAX_NU = 16
+
+
+class GeneralDesc(C.Structure):
+    _fields_ = [("d", C.c_int32), ("n_nodes", C.c_int32 * MAX_D), ("n_unodes", C.c_int32 * MAX_D),
+                ("h", C.c_double), ("rho", C.c_double), ("p_max", C.c_double), ("u_max", C.c_double),
+                ("u_init", C.c_double * MAX_D), ("drift_dev", C.c_void_p), ("payoff_dev", C.c_void_p)]
+
+
 _lib: Optional[C.CDLL] = None
 
 
@@ -91,6 +100,17 @@ def lib() -> C.CDLL:
     L.cg_warm_start.argtypes = [vp, vp, fp, C.c_double, vp, C.c_size_t, C.c_int32, ip]
     L.cg_solve_warm.argtypes = [vp, vp, fp, C.c_double, C.c_int32, C.c_double, C.c_int32, vp, C.c_size_t,
                                 C.c_int32, ip, dp, ip]
+    gp = C.POINTER(GeneralDesc)
+    L.cg_general_nodes.argtypes = [gp, dp, dp]
+    L.cg_general_workspace_bytes.restype = C.c_size_t
+    L.cg_general_workspace_bytes.argtypes = [gp]
+    L.cg_general_init.argtypes = [gp, vp, C.c_size_t, vp, C.POINTER(vp)]
+    L.cg_general_step.argtypes = [vp, C.c_int32, dp]
+    L.cg_general_solve.argtypes = [vp, C.c_int32, C.c_double, ip, dp]
+    L.cg_general_get_state.argtypes = [vp, vp, vp, ip]
+    L.cg_general_set_state.argtypes = [vp, vp, vp]
+    L.cg_general_profile.argtypes = [vp, C.c_int, dp, C.POINTER(C.c_int64)]
+    L.cg_general_destroy.argtypes = [vp]
     _lib = L
     return L
 
@@ -479,3 +499,120 @@ def chebyshev_eval(coef, x, precision: int = FP64, stream=None, out=None):
                                    C.c_void_p(_stream(stream))))
     out._ws = ws  # keep the workspace alive with the result's lifetime
     return out
+
+
+# ---- general form (non-separable controls, anisotropic grids) ----
+
+def _gdesc(game, drift=None, payoff=None) -> GeneralDesc:
+    """cg_general_desc from an object with d, n_p, n_u, h, rho, p_max, u_max
+    and u_init (None: u_max / 2) fields."""
+    D = GeneralDesc()
+    D.d = int(game.d)
+    for l in range(int(game.d)):
+        D.n_nodes[l] = int(game.n_p[l])
+        D.n_unodes[l] = int(game.n_u[l])
+    D.h, D.rho, D.p_max, D.u_max = float(game.h), float(game.rho), float(game.p_max), float(game.u_max)
+    u0 = getattr(game, "u_init", None)
+    for l in range(int(game.d)):
+        D.u_init[l] = 0.5 * float(game.u_max) if u0 is None else float(u0[l])
+    D.drift_dev = None if drift is None else drift.data_ptr()
+    D.payoff_dev = None if payoff is None else payoff.data_ptr()
+    return D
+
+
+def general_nodes(game):
+    """(state nodes per dimension, control nodes per player), physical units,
+    from cg_general_nodes: the points where the drift and payoff are sampled."""
+    D = _gdesc(game)
+    pn = np.empty(int(sum(game.n_p)))
+    un = np.empty(int(sum(game.n_u)))
+    _check(lib().cg_general_nodes(C.byref(D), pn.ctypes.data_as(C.POINTER(C.c_double)),
+                                  un.ctypes.data_as(C.POINTER(C.c_double))))
+    cp = np.cumsum([0] + list(game.n_p))
+    cu = np.cumsum([0] + list(game.n_u))
+    return ([pn[cp[l]:cp[l + 1]] for l in range(game.d)], [un[cu[l]:cu[l + 1]] for l in range(game.d)])
+
+
+class ChebGeneral:
+    """Handle of the general form (cg_general*): the game is given by its
+    drift and payoff samples, device tensors [d][N_P][U_P] (FP64)."""
+
+    def __init__(self, game, drift, payoff, stream=None):
+        import torch
+        drift = drift.to(device="cuda", dtype=torch.float64).contiguous()
+        payoff = payoff.to(device="cuda", dtype=torch.float64).contiguous()
+        NP, UP = int(np.prod(game.n_p[:game.d])), int(np.prod(game.n_u[:game.d]))
+        for t, name in ((drift, "drift"), (payoff, "payoff")):
+            if t.numel() != int(game.d) * NP * UP:
+                raise ChebGameError(EINVAL, f"{name} has {t.numel()} values, expected d N_P U_P = "
+                                            f"{int(game.d) * NP * UP}")
+        desc = _gdesc(game, drift, payoff)
+        L = lib()
+        nbytes = int(L.cg_general_workspace_bytes(C.byref(desc)))
+        if nbytes == 0:  # invalid description: let init report the specific status
+            h = C.c_void_p()
+            _check(L.cg_general_init(C.byref(desc), None, 0, C.c_void_p(_stream(stream)), C.byref(h)))
+            raise ChebGameError(EINVAL, last_error())
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        self.stream = stream
+        self.d = int(game.d)
+        self.n_p, self.n_u = tuple(int(x) for x in game.n_p[:self.d]), tuple(int(x) for x in game.n_u[:self.d])
+        self.NP = int(np.prod(self.n_p))
+        h = C.c_void_p()
+        _check(L.cg_general_init(C.byref(desc), C.c_void_p(self.ws.data_ptr()), nbytes,
+                                 C.c_void_p(_stream(stream)), C.byref(h)))
+        self.handle = h
+
+    @classmethod
+    def from_game(cls, game, stream=None):
+        """Samples the game's drift(P, Uc) and payoff(P, Uc) (its `values`
+        method) at the grid cg_general_nodes returns, then initialises."""
+        import torch
+        pn, un = general_nodes(game)
+        g, G = game.values(pn, un)
+        return cls(game, torch.from_numpy(g), torch.from_numpy(G), stream)
+
+    def step(self, nsteps: int = 1, sync: bool = True) -> Optional[float]:
+        r = C.c_double()
+        _check(lib().cg_general_step(self.handle, nsteps, C.byref(r) if sync else None))
+        return r.value if sync else None
+
+    def solve(self, max_steps: int, tol: float = 0.0) -> Tuple[int, int, float]:
+        n = C.c_int32()
+        r = C.c_double()
+        rc = _check(lib().cg_general_solve(self.handle, max_steps, float(tol), C.byref(n), C.byref(r)))
+        return rc, n.value, r.value
+
+    def get_state(self):
+        import torch
+        V = torch.empty((self.d, self.NP), dtype=torch.float64, device="cuda")
+        U = torch.empty_like(V)
+        r = C.c_int32()
+        _check(lib().cg_general_get_state(self.handle, C.c_void_p(V.data_ptr()), C.c_void_p(U.data_ptr()),
+                                          C.byref(r)))
+        return V, U, r.value
+
+    def set_state(self, V, U=None):
+        import torch
+        V = torch.as_tensor(V).to(device="cuda", dtype=torch.float64).contiguous().reshape(self.d, self.NP)
+        if U is not None:
+            U = torch.as_tensor(U).to(device="cuda", dtype=torch.float64).contiguous().reshape(self.d, self.NP)
+        self._pin = (V, U)
+        _check(lib().cg_general_set_state(self.handle, C.c_void_p(V.data_ptr()),
+                                          C.c_void_p(U.data_ptr()) if U is not None else None))
+
+    def profile(self, enable: bool = True):
+        """(ms per phase [transform, points, evaluation, line], iterations
+        timed) since the last call; (re)arms timing."""
+        ms = (C.c_double * 4)()
+        n = C.c_int64()
+        _check(lib().cg_general_profile(self.handle, 1 if enable else 0, ms, C.byref(n)))
+        return list(ms), n.value
+
+    def __del__(self):
+        try:
+            if getattr(self, "handle", None) is not None and _lib is not None:
+                _lib.cg_general_destroy(self.handle)
+                self.handle = None
+        except Exception:
+            pass

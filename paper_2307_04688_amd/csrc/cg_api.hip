@@ -220,6 +220,7 @@ int set_error(int code, const char *msg)
     g_last_error = msg;
     return code;
 }
+int require_gfx950() { return check_device(); }
 }  // namespace cg
 
 namespace {

@@ -29,10 +29,12 @@ __device__ __forceinline__ __bf16 to_elem<__bf16>(double v) { return (__bf16)(fl
 template <typename T>
 __global__ __launch_bounds__(256) void k_pack_eval(const double *__restrict__ coef, T *__restrict__ Bp, int d,
                                                    int n0, int n1, int n2, int n3, int N4, int NC, long long K,
-                                                   long long Kpad)
+                                                   long long Kpad, long long coef_stride)
 {
     const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= Kpad * NC) return;
+    coef += blockIdx.y * coef_stride;  // member y of a batch of tensors of one shape
+    Bp += blockIdx.y * Kpad * NC;
     const int n[4] = {n0, n1, n2, n3};
     const int col = (int)(e % NC);
     long long kidx = e / NC;
@@ -79,11 +81,18 @@ struct MfmaF<float> {
 };
 
 // FP64 / FP32 evaluation: K-steps of 4, one A and one B element per lane.
+// Member blockIdx.y of a batch uses packed operand Bp + y bp_stride, points
+// X + x_off[y] d and outputs out + x_off[y] (npts[y] of them).
 template <typename TE, typename TO, int D, int N4, int NC, int RB>
 __global__ __launch_bounds__(256) void k_eval_mfma(const TE *__restrict__ Bp, const double *__restrict__ X,
-                                                   TO *__restrict__ out, long long npts, int n0, int n1,
+                                                   TO *__restrict__ out, EvalBatch bt, int n0, int n1,
                                                    int nlast)
 {
+    const long long npts = bt.npts[blockIdx.y];
+    if ((long long)blockIdx.x * (4 * RB * 16) >= npts) return;  // whole block beyond this member
+    Bp += blockIdx.y * bt.bp_stride;
+    X += bt.x_off[blockIdx.y] * D;
+    out += bt.x_off[blockIdx.y];
     constexpr int NCB = NC / 16;
     constexpr int ROWS_W = RB * 16;
     constexpr int ROWS_B = 4 * ROWS_W;
@@ -488,20 +497,23 @@ size_t eval_ws_bytes(int d, const int *n, int precision)
 }
 
 template <typename TE, typename TO, int D, int N4>
-static hipError_t launch_eval_dn(const void *Bp, const double *x, TO *out, long long npts, const int *n,
-                                 hipStream_t s)
+static hipError_t launch_eval_dn(const void *Bp, const double *x, TO *out, const EvalBatch &bt, int count,
+                                 const int *n, hipStream_t s)
 {
     constexpr int NC32 = 32, NC16 = 16;
     constexpr int RB = 4;
     const int rows_b = 4 * RB * 16;
-    const unsigned blocks = (unsigned)((npts + rows_b - 1) / rows_b);
+    long long mx = 0;
+    for (int b = 0; b < count; ++b) mx = bt.npts[b] > mx ? bt.npts[b] : mx;
+    if (mx == 0) return hipSuccess;
+    const unsigned blocks = (unsigned)((mx + rows_b - 1) / rows_b);
     const int n0 = D >= 3 ? n[0] : 1, n1 = D >= 4 ? n[1] : 1;
     if (n[D - 1] <= 16)
-        hipLaunchKernelGGL((k_eval_mfma<TE, TO, D, N4, NC16, RB>), dim3(blocks), dim3(256), 0, s,
-                           (const TE *)Bp, x, out, npts, n0, n1, n[D - 1]);
+        hipLaunchKernelGGL((k_eval_mfma<TE, TO, D, N4, NC16, RB>), dim3(blocks, (unsigned)count), dim3(256), 0, s,
+                           (const TE *)Bp, x, out, bt, n0, n1, n[D - 1]);
     else
-        hipLaunchKernelGGL((k_eval_mfma<TE, TO, D, N4, NC32, RB>), dim3(blocks), dim3(256), 0, s,
-                           (const TE *)Bp, x, out, npts, n0, n1, n[D - 1]);
+        hipLaunchKernelGGL((k_eval_mfma<TE, TO, D, N4, NC32, RB>), dim3(blocks, (unsigned)count), dim3(256), 0, s,
+                           (const TE *)Bp, x, out, bt, n0, n1, n[D - 1]);
     return hipGetLastError();
 }
 
@@ -557,14 +569,14 @@ static hipError_t launch_eval_bf16_dn(const double *coef, void *ws, const double
     }
 
 template <int D>
-static hipError_t launch_eval_d(const void *Bp, const double *x, void *out, long long npts, const int *n,
-                                int precision, hipStream_t s)
+static hipError_t launch_eval_d(const void *Bp, const double *x, void *out, const EvalBatch &bt, int count,
+                                const int *n, int precision, hipStream_t s)
 {
     const int N4 = round4(n[D - 2]);
     if (precision == CG_FP64) {
-        CG_N4_SWITCH(N4, return (launch_eval_dn<double, double, D, N4c>(Bp, x, (double *)out, npts, n, s)))
+        CG_N4_SWITCH(N4, return (launch_eval_dn<double, double, D, N4c>(Bp, x, (double *)out, bt, count, n, s)))
     } else {
-        CG_N4_SWITCH(N4, return (launch_eval_dn<float, float, D, N4c>(Bp, x, (float *)out, npts, n, s)))
+        CG_N4_SWITCH(N4, return (launch_eval_dn<float, float, D, N4c>(Bp, x, (float *)out, bt, count, n, s)))
     }
     return hipErrorInvalidValue;
 }
@@ -608,16 +620,51 @@ hipError_t launch_eval(int d, const int *n, const double *coef, const double *x,
     const unsigned pb = (unsigned)((K * NC + 255) / 256);
     if (precision == CG_FP64)
         hipLaunchKernelGGL(k_pack_eval<double>, dim3(pb), dim3(256), 0, s, coef, (double *)ws, d, nn[0], nn[1], nn[2],
-                           nn[3], N4, NC, K, K);
+                           nn[3], N4, NC, K, K, 0LL);
     else
         hipLaunchKernelGGL(k_pack_eval<float>, dim3(pb), dim3(256), 0, s, coef, (float *)ws, d, nn[0], nn[1], nn[2],
-                           nn[3], N4, NC, K, K);
+                           nn[3], N4, NC, K, K, 0LL);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    EvalBatch bt = {};
+    bt.npts[0] = npts;
     switch (d) {
-        case 2: return launch_eval_d<2>(ws, x, out, npts, n, precision, s);
-        case 3: return launch_eval_d<3>(ws, x, out, npts, n, precision, s);
-        case 4: return launch_eval_d<4>(ws, x, out, npts, n, precision, s);
+        case 2: return launch_eval_d<2>(ws, x, out, bt, 1, n, precision, s);
+        case 3: return launch_eval_d<3>(ws, x, out, bt, 1, n, precision, s);
+        case 4: return launch_eval_d<4>(ws, x, out, bt, 1, n, precision, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+size_t eval_packed_elems(int d, const int *n)
+{
+    const int N4 = round4(n[d - 2]);
+    const int NC = n[d - 1] <= 16 ? 16 : 32;
+    return (size_t)(eval_K(d, n, N4) * NC);
+}
+
+hipError_t pack_eval_f64(int d, const int *n, const double *coef, long long count, long long coef_stride,
+                         double *Bp, hipStream_t s)
+{
+    if (d < 2 || count <= 0) return d < 2 ? hipErrorInvalidValue : hipSuccess;
+    const int N4 = round4(n[d - 2]);
+    const int NC = n[d - 1] <= 16 ? 16 : 32;
+    const long long K = eval_K(d, n, N4);
+    const int nn[4] = {n[0], n[1], d > 2 ? n[2] : 1, d > 3 ? n[3] : 1};
+    const unsigned pb = (unsigned)((K * NC + 255) / 256);
+    hipLaunchKernelGGL(k_pack_eval<double>, dim3(pb, (unsigned)count), dim3(256), 0, s, coef, Bp, d, nn[0], nn[1],
+                       nn[2], nn[3], N4, NC, K, K, coef_stride);
+    return hipGetLastError();
+}
+
+hipError_t eval_f64_batch(int d, const int *n, const double *Bp, const double *x, double *out, const EvalBatch &bt,
+                          int count, hipStream_t s)
+{
+    if (count < 1 || count > kMaxD) return hipErrorInvalidValue;
+    switch (d) {
+        case 2: return launch_eval_d<2>(Bp, x, out, bt, count, n, CG_FP64, s);
+        case 3: return launch_eval_d<3>(Bp, x, out, bt, count, n, CG_FP64, s);
+        case 4: return launch_eval_d<4>(Bp, x, out, bt, count, n, CG_FP64, s);
     }
     return hipErrorInvalidValue;
 }

@@ -136,6 +136,22 @@ hipError_t launch_eval(int d, const int *n, const double *coef, const double *x,
                        void *out, int precision, void *ws, size_t ws_bytes, hipStream_t s);
 size_t eval_ws_bytes(int d, const int *n, int precision);
 
+// Batched FP64 evaluation of up to kMaxD series of one shape n: member b
+// uses packed operand Bp + b bp_stride and the npts[b] points starting at
+// row x_off[b] of x (outputs at the same offsets).
+struct EvalBatch {
+    long long bp_stride;
+    long long x_off[kMaxD];
+    long long npts[kMaxD];
+};
+// Elements of one packed FP64 operand of shape n.
+size_t eval_packed_elems(int d, const int *n);
+// Packs 'count' coefficient tensors (coef + b coef_stride) into Bp + b eval_packed_elems.
+hipError_t pack_eval_f64(int d, const int *n, const double *coef, long long count, long long coef_stride,
+                         double *Bp, hipStream_t s);
+hipError_t eval_f64_batch(int d, const int *n, const double *Bp, const double *x, double *out, const EvalBatch &bt,
+                          int count, hipStream_t s);
+
 // One 16 x 16 tile of C = op(A) op(B) (NP x NP, NP = 16 or 32) with both
 // operands in LDS (row stride LD doubles, zero beyond the data), on
 // v_mfma_f64_16x16x4f64.  Wave w < (NP/16)^2 computes tile (ti, tj) = (w / T,
@@ -171,5 +187,7 @@ hipStream_t game_stream(const cg_game *g);
 void default_tiles(int d, int precision, int &rb, int &ocb);
 // Records an error message for cg_last_error(); returns code.
 int set_error(int code, const char *msg);
+// CG_OK if the current device is a gfx950, else CG_EDEVICE with a message.
+int require_gfx950();
 
 }  // namespace cg

@@ -4,8 +4,8 @@
 // Along one mode of size N (n = N-1 intervals) the rule is the DCT-I
 //   c_l = (w_l / n) sum_k e_k F_k cos(pi l k / n),  w_0 = w_n = 1, else 2,
 //   e_0 = e_n = 1/2, else 1.
-// One thread owns one fibre: it loads the N values into registers, then
-// writes the N coefficients back, so a pass may run in place.  The N x N
+// The generic pass (any shape, any batch) stages whole fibres in LDS and
+// writes one coefficient per thread, so it may run in place; the N x N
 // matrix is built in LDS by each block.  The transform is a small share of a
 // step (2 d N^(d+1) flops per tensor against 2 N^(2d) for the contraction).
 #include "cg_internal.h"
@@ -21,27 +21,35 @@ __device__ inline double dct1_entry(int l, int k, int N)
     return v * ((l == 0 || l == n) ? 1.0 : 2.0) / (double)n;
 }
 
+// One pass along a mode: a block owns 256 / N whole fibres, stages them in
+// LDS and writes their N coefficients with one thread per output (so a pass
+// may run in place: every fibre is read before any of it is written, and
+// blocks own disjoint fibres).  Consecutive threads take consecutive fibres
+// of the same coefficient, which are adjacent in memory for every mode but
+// the last.
 __global__ __launch_bounds__(256) void k_transform_mode(const double *in, double *out, long long fibers,
                                                         long long fpt, long long stride, int N,
                                                         long long total)
 {
     __shared__ double Dm[kMaxN * kMaxN];
+    __shared__ double X[256];
     for (int e = threadIdx.x; e < N * N; e += blockDim.x) Dm[e] = dct1_entry(e / N, e % N, N);
+    const int FB = 256 / N;
+    const int t = threadIdx.x;
+    const int l = t / FB, fl = t % FB;
+    const long long f = (long long)blockIdx.x * FB + fl;
+    const bool ok = l < N && f < fibers;
+    long long base = 0;
+    if (ok) {
+        const long long b = f / fpt, r = f % fpt;
+        const long long o = r / stride, i = r % stride;
+        base = b * total + o * (long long)N * stride + i;
+        X[fl * N + l] = in[base + l * stride];
+    }
     __syncthreads();
-    const long long f = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (f >= fibers) return;
-    const long long b = f / fpt, r = f % fpt;
-    const long long o = r / stride, i = r % stride;
-    const long long base = b * total + o * (long long)N * stride + i;
-    double x[kMaxN];
-#pragma unroll
-    for (int k = 0; k < kMaxN; ++k)
-        if (k < N) x[k] = in[base + k * stride];
-    for (int l = 0; l < N; ++l) {
+    if (ok) {
         double acc = 0.0;
-#pragma unroll
-        for (int k = 0; k < kMaxN; ++k)
-            if (k < N) acc = fma(Dm[l * N + k], x[k], acc);
+        for (int k = 0; k < N; ++k) acc = fma(Dm[l * N + k], X[fl * N + k], acc);
         out[base + l * stride] = acc;
     }
 }
@@ -56,7 +64,8 @@ hipError_t launch_transform_mode(const double *in, double *out, int d, const int
     const long long fibers = fpt * batch;
     if (fibers == 0) return hipSuccess;
     const int threads = 256;
-    const long long blocks = (fibers + threads - 1) / threads;
+    const long long fb = threads / n[mode];
+    const long long blocks = (fibers + fb - 1) / fb;
     hipLaunchKernelGGL(k_transform_mode, dim3((unsigned)blocks), dim3(threads), 0, s, in, out, fibers, fpt,
                        stride, n[mode], total);
     return hipGetLastError();

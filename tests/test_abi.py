@@ -61,3 +61,37 @@ def test_eval_workspace_sizes():
     b16 = L.cg_eval_workspace_bytes(4, n, cg.BF16)
     assert b64 >= 24 ** 3 * 32 * 8 and b32 >= 24 ** 3 * 32 * 4 and b16 >= 24 ** 3 * 32 * 2
     assert L.cg_eval_workspace_bytes(1, n, cg.FP64) == 0
+
+
+def test_general_desc_layout_and_host_calls(orc):
+    # int32 d, 2 x 4 int32, 4 doubles, 4 doubles, 2 pointers (+4 bytes padding after the ints)
+    assert C.sizeof(cg.GeneralDesc) == 40 + 32 + 32 + 2 * C.sizeof(C.c_void_p)
+    gg = W.general_game(3, (7, 5, 9), (4, 6, 3), seed=2)
+    # the library's grid is the oracle's (same Lobatto formula, computed apart)
+    pn, un = cg.general_nodes(gg)
+    po, uo = orc.gen_grids(gg)
+    for a, b in zip(pn + un, po + uo):
+        assert a.shape == b.shape and np.max(np.abs(a - b)) <= 2e-16
+    assert pn[0][0] == gg.p_max and un[1][0] == gg.u_max and un[1][-1] == 0.0
+    L = cg.lib()
+    D = cg._gdesc(gg)
+    assert L.cg_general_workspace_bytes(C.byref(D)) == 0 and "drift" in cg.last_error()
+    D.drift_dev = D.payoff_dev = 256  # any non-null pointer: the size query reads nothing
+    nb = L.cg_general_workspace_bytes(C.byref(D))
+    NP, UP, NPT = 7 * 5 * 9, 4 * 6 * 3, 7 * 5 * 9 * (4 + 6 + 3)
+    assert nb >= 8 * (2 * 3 * NP * UP + NPT * (3 + 2) + 3 * 3 * NP)
+    # init rejects a missing workspace before touching any device
+    h = C.c_void_p()
+    assert L.cg_general_init(C.byref(D), None, 0, None, C.byref(h)) == cg.ENOMEM
+    for field, val, msg in (("n_unodes", 17, "n_unodes"), ("n_nodes", 2, "n_nodes"), ("n_nodes", 33, "n_nodes")):
+        D2 = cg._gdesc(gg)
+        D2.drift_dev = D2.payoff_dev = 256
+        getattr(D2, field)[1] = val
+        assert L.cg_general_workspace_bytes(C.byref(D2)) == 0 and msg in cg.last_error()
+    D2 = cg._gdesc(gg)
+    D2.drift_dev = D2.payoff_dev = 256
+    D2.u_init[2] = 1.5
+    assert L.cg_general_workspace_bytes(C.byref(D2)) == 0 and "u_init" in cg.last_error()
+    D2.u_init[2] = 0.5
+    D2.d = 5
+    assert L.cg_general_workspace_bytes(C.byref(D2)) == 0

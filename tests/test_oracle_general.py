@@ -30,7 +30,8 @@ def test_values_layout(orc):
     assert np.allclose(g[:, j, t], gg.drift(p, u), rtol=0, atol=1e-15)
     assert np.allclose(G[:, j, t], gg.payoff(p, u), rtol=0, atol=1e-15)
     # the log benefit, competition and stock coupling, written out for player 1
-    ref = gg.A[1] * np.log1p(u[1]) - 0.5 * gg.phi[1] * p[1] ** 2 - gg.kappa[1] * u[1] * (u[0] + u[2]) / 2
+    ref = (u[1] * (gg.A[1] - 0.5 * u[1]) + 0.1 * np.log1p(u[1]) - 0.5 * gg.phi[1] * p[1] ** 2
+           - gg.kappa[1] * u[1] * (u[0] + u[2]) / 2)
     assert abs(G[1, j, t] - ref) < 1e-15
     ref = gg.M[2] @ p + gg.B[2] @ u - gg.eta[2] * p[2] * u[2]
     assert abs(g[2, j, t] - ref) < 1e-15

@@ -236,7 +236,8 @@ class GeneralGame:
 
     drift     g_k(p, u) = (M p)_k + sum_l B_kl u_l - eta_k p_k u_k
     payoff    G_i(p, u) = b_i(u_i) - phi_i p_i^2 / 2 - kappa_i u_i mean_{l != i} u_l
-              with b_i(u) = A_i log(1 + u) ("log") or u (A_i - u / 2) ("quadratic")
+              with b_i(u) = u (A_i - u / 2) + lam log(1 + u) ("log", lam = 0.1)
+              or u (A_i - u / 2) ("quadratic")
 
     B's off-diagonal entries carry emissions across borders, eta couples the
     stock to the emission factor, kappa is a competition term; with B
@@ -278,10 +279,9 @@ class GeneralGame:
         Pm, Um = np.moveaxis(P, -1, 0), np.moveaxis(Uc, -1, 0)
         sh = (-1,) + (1,) * (P.ndim - 1)
         A, phi, kap = self.A.reshape(sh), self.phi.reshape(sh), self.kappa.reshape(sh)
+        ben = Um * (A - 0.5 * Um)
         if self.benefit == "log":
-            ben = A * np.log1p(Um)
-        else:
-            ben = Um * (A - 0.5 * Um)
+            ben = ben + LOG_BENEFIT * np.log1p(Um)
         others = (Um.sum(axis=0, keepdims=True) - Um) / max(self.d - 1, 1)
         return ben - 0.5 * phi * Pm * Pm - kap * Um * others
 
@@ -296,19 +296,25 @@ class GeneralGame:
         return np.ascontiguousarray(g), np.ascontiguousarray(G)
 
 
+# weight of the non-polynomial part of the benefit in general games
+LOG_BENEFIT = 0.1
+
+
 def general_game(d: int, n_p, n_u, seed: int, instance: int = 0, *, h: float = 1e-2,
                  spill: float = 0.3, benefit: str = "log") -> GeneralGame:
     """Seeded non-separable game: the per-player parameters of `make_game`
     (per_player=True) plus cross-border emission shares B_kl = spill beta_l
     w_kl (w ~ U[0,1)), stock-emission coupling eta_k ~ 0.5 U[0,1) and
-    competition kappa_i ~ 0.3 (0.5 + U[0,1))."""
+    competition kappa_i ~ 0.1 (0.5 + U[0,1)).  The benefit keeps the LQ
+    game's curvature (interior controls, best responses that damp each
+    other under simultaneous updates) and adds a non-polynomial term."""
     base = make_game(d, 3, seed, instance, h=h, per_player=True)
     M = base.K / base.m[:, None] - np.diag(base.c)
     w = uniform(seed, 3000 + instance, np.arange(d * d + 2 * d, dtype=np.uint64))
     B = spill * base.beta[None, :] * w[:d * d].reshape(d, d)
     np.fill_diagonal(B, base.beta)
     eta = 0.5 * w[d * d:d * d + d]
-    kappa = 0.3 * (0.5 + w[d * d + d:])
+    kappa = 0.1 * (0.5 + w[d * d + d:])
     return GeneralGame(d, tuple(int(x) for x in n_p), tuple(int(x) for x in n_u), h, base.rho,
                        base.p_max, base.u_max, M, B, eta, base.A.copy(), base.phi.copy(), kappa, benefit)
 
