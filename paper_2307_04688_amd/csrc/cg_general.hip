@@ -58,7 +58,7 @@ struct GenStatus {
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct GenLayout {
-    size_t gc, st, V, U, coef, gcoef, pcoef, pts, psamp, ev, blk, evws, evws_bytes, total;
+    size_t gc, st, V, U, coef, cc, pts, psamp, ev, blk, evws, evws_bytes, total;
 };
 
 __global__ void k_gen_init(const GenConst *__restrict__ gc, GenStatus *st, double *V, double *U)
@@ -89,22 +89,45 @@ __global__ void k_gen_arm(GenStatus *st, double tol, int clear_done)
     }
 }
 
-// Step 1 for (node, player) pairs: 16 lanes per pair, 16 pairs per block.
-// Pair q = blockIdx.x * 16 + group is node j = q / D, player i = q % D, so
-// the D players of a node are adjacent groups and share the node's drift
-// tensors through the caches.  Each lane contracts a strided share of the
+// Sum over the 16 lanes of a DPP row (a 16-lane group), returned in every
+// lane of the row: pairs and quads by quad permutations, then rotations of
+// the row by 4 and 8 lanes (VALU data movement, no LDS traffic).  The last
+// two steps add the four quad sums in an order that depends on the quad, so
+// lanes may differ in the last bit; each is deterministic.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+__device__ __forceinline__ double row16_sum(double v)
+{
+    v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
+    v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
+    v += dpp_f64<0x124>(v);  // row_ror:4
+    v += dpp_f64<0x128>(v);  // row_ror:8
+    return v;
+}
+
+// Step 1 for (node, player) pairs: 16 lanes per pair, G pairs per block (G
+// the largest multiple of D that fits 256 threads).  Pair q = blockIdx.x G +
+// group is node j = q / D, player i = q % D, so the D players of a node are
+// groups of one block and share the node's drift tensors (one contiguous
+// block per node in the node-major layout) through the caches.  Each lane contracts a strided share of the
 // outer control indices; the 16 partial sums of every coefficient are then
-// combined by shuffles within the group.  NUM >= every n_unodes, a multiple
+// combined within the group (row16_sum).  NUM >= every n_unodes, a multiple
 // of 4 (register arrays stay compile-time sized).
 template <int D, int NUM>
 __global__ __launch_bounds__(256) void k_gen_points(const GenConst *__restrict__ gc,
                                                     const GenStatus *__restrict__ st,
                                                     const double *__restrict__ U,
-                                                    const double *__restrict__ gcoef,
-                                                    const double *__restrict__ pcoef, double *__restrict__ pts,
+                                                    const double *__restrict__ cc, double *__restrict__ pts,
                                                     double *__restrict__ psamp)
 {
-    constexpr int L = 16, G = 256 / L;
+    constexpr int L = 16, G = (256 / L / D) * D;
     __shared__ double Tb[G][D][NUM];
     if (st->converged) return;
     const int tid = threadIdx.x, grp = tid / L, lane = tid % L;
@@ -136,8 +159,12 @@ __global__ __launch_bounds__(256) void k_gen_points(const GenConst *__restrict__
     for (int k = 0; k <= D; ++k)
 #pragma unroll
         for (int a = 0; a < NUM; ++a) acc[k][a] = 0.0;
-    const double *gbase = gcoef + j * UP;                        // component k at + k NP UP
-    const double *pbase = pcoef + ((long long)i * NP + j) * UP;  // payoff of player i
+    const double *gbase = cc + j * (2 * D) * UP;  // drift component k at + k UP
+    const double *pbase = gbase + (D + i) * UP;    // payoff of player i
+    // The loads of one outer index are issued together: no data-dependent
+    // branch between them (entries a >= nui read a valid address, entry
+    // nui - 1, and are weighted by zero).
+#pragma unroll 2
     for (int o = lane; o < nouter; o += L) {
         // o enumerates the control modes other than i in C order
         int rem = o, base = 0;
@@ -150,26 +177,26 @@ __global__ __launch_bounds__(256) void k_gen_points(const GenConst *__restrict__
             base += a * gc->ustride[l];
             w *= Tb[grp][l][a];
         }
+        double v[D + 1][NUM];
 #pragma unroll
         for (int a = 0; a < NUM; ++a) {
-            if (a < nui) {
+            const int off = base + (a < nui ? a : nui - 1) * si;
 #pragma unroll
-                for (int k = 0; k < D; ++k)
-                    acc[k][a] = fma(gbase[(long long)k * NP * UP + base + a * si], w, acc[k][a]);
-                acc[D][a] = fma(pbase[base + a * si], w, acc[D][a]);
-            }
+            for (int k = 0; k < D; ++k) v[k][a] = gbase[k * UP + off];
+            v[D][a] = pbase[off];
+        }
+#pragma unroll
+        for (int a = 0; a < NUM; ++a) {
+            const double wa = a < nui ? w : 0.0;
+#pragma unroll
+            for (int k = 0; k <= D; ++k) acc[k][a] = fma(v[k][a], wa, acc[k][a]);
         }
     }
 #pragma unroll
     for (int a = 0; a < NUM; ++a) {
         if (a < nui) {
 #pragma unroll
-            for (int k = 0; k <= D; ++k) {
-                double v = acc[k][a];
-#pragma unroll
-                for (int off = L / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, L);
-                acc[k][a] = v;
-            }
+            for (int k = 0; k <= D; ++k) acc[k][a] = row16_sum(acc[k][a]);
         }
     }
     if (lane < nui) {
@@ -272,6 +299,20 @@ __global__ __launch_bounds__(256) void k_gen_finish(GenStatus *st, const double 
         } else if (st->tol > 0.0 && r < st->tol) {
             st->converged = 1;
         }
+    }
+}
+
+// Step 0 staging: the caller's samples drift[k][j][t] and payoff[i][j][t]
+// into the node-major layout cc[j][0..d) (drift), cc[j][d..2d) (payoffs), so
+// that everything Step 1 reads for one node is one contiguous block.
+__global__ void k_gen_gather(double *cc, const double *drift, const double *payoff, int d, long long NP, long long UP,
+                             long long n)
+{
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+         e += (long long)gridDim.x * blockDim.x) {
+        const long long t = e % UP, r = e / UP, j = r % NP, k = r / NP;
+        cc[(j * 2 * d + k) * UP + t] = drift[e];
+        cc[(j * 2 * d + d + k) * UP + t] = payoff[e];
     }
 }
 
@@ -394,8 +435,7 @@ GenLayout layout(const GenConst &c)
     L.V = o; o = align256(o + sizeof(double) * d * NP);
     L.U = o; o = align256(o + sizeof(double) * d * NP);
     L.coef = o; o = align256(o + sizeof(double) * d * NP);
-    L.gcoef = o; o = align256(o + sizeof(double) * d * NP * UP);
-    L.pcoef = o; o = align256(o + sizeof(double) * d * NP * UP);
+    L.cc = o; o = align256(o + sizeof(double) * 2 * d * NP * UP);
     L.pts = o; o = align256(o + sizeof(double) * NPT * d);
     L.psamp = o; o = align256(o + sizeof(double) * NPT);
     L.ev = o; o = align256(o + sizeof(double) * NPT);
@@ -430,10 +470,11 @@ namespace {
 template <int D, int NUM>
 hipError_t launch_points_n(const cg_general *g)
 {
+    constexpr int G = (16 / D) * D;  // pairs per block
     const long long pairs = g->hc.NP * D;
-    hipLaunchKernelGGL((k_gen_points<D, NUM>), dim3((unsigned)((pairs + 15) / 16)), dim3(256), 0, g->stream,
+    hipLaunchKernelGGL((k_gen_points<D, NUM>), dim3((unsigned)((pairs + G - 1) / G)), dim3(16 * G), 0, g->stream,
                        g->at<GenConst>(g->L.gc), g->at<GenStatus>(g->L.st), g->at<double>(g->L.U),
-                       g->at<double>(g->L.gcoef), g->at<double>(g->L.pcoef), g->at<double>(g->L.pts),
+                       g->at<double>(g->L.cc), g->at<double>(g->L.pts),
                        g->at<double>(g->L.psamp));
     return hipGetLastError();
 }
@@ -572,11 +613,16 @@ int cg_general_init(const cg_general_desc *desc, void *ws_dev, size_t ws_bytes, 
         }
     }
     hipError_t e = hipMemcpyAsync(g->ws + g->L.gc, &g->hc, sizeof(GenConst), hipMemcpyHostToDevice, g->stream);
-    // Step 0: control polynomials of every node, drift components then payoffs
+    // Step 0: control polynomials of every node (node-major: drift components,
+    // then payoffs), by the transform in place
+    if (e == hipSuccess) {
+        const long long n = (long long)c.d * c.NP * c.UP;
+        hipLaunchKernelGGL(k_gen_gather, dim3(1024), dim3(256), 0, g->stream, g->at<double>(g->L.cc), desc->drift_dev,
+                           desc->payoff_dev, c.d, c.NP, c.UP, n);
+        e = hipGetLastError();
+    }
     if (e == hipSuccess)
-        e = run_transform(c.d, c.nu, desc->drift_dev, g->at<double>(g->L.gcoef), (long long)c.d * c.NP, g->stream);
-    if (e == hipSuccess)
-        e = run_transform(c.d, c.nu, desc->payoff_dev, g->at<double>(g->L.pcoef), (long long)c.d * c.NP, g->stream);
+        e = run_transform(c.d, c.nu, g->at<double>(g->L.cc), g->at<double>(g->L.cc), 2LL * c.d * c.NP, g->stream);
     if (e == hipSuccess) {
         hipLaunchKernelGGL(k_gen_init, dim3(256), dim3(256), 0, g->stream, g->at<GenConst>(g->L.gc),
                            g->at<GenStatus>(g->L.st), g->at<double>(g->L.V), g->at<double>(g->L.U));

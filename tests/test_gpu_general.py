@@ -88,6 +88,19 @@ def test_largest_sizes(cg, orc):
     assert relmax(Vg, Vo) < V_TOL and np.max(np.abs(Ug - Uo)) < U_TOL
 
 
+@pytest.mark.parametrize("d,n_p,n_u", [
+    (3, (5, 4, 6), (16, 12, 9)),
+    (4, (3, 4, 3, 4), (8, 5, 7, 6)),
+])
+def test_large_control_grids(cg, orc, d, n_p, n_u):
+    # control grids whose coefficients do not fit the LDS-staged Step 1
+    # (more than 64 KiB per node): the streaming kernel runs instead
+    gg = W.general_game(d, n_p, n_u, seed=35)
+    say(f"  general d={d} n_p={n_p} n_u={n_u} (U_P = {int(np.prod(n_u))})")
+    Vg, Ug, rg, Vo, Uo, ro = _run_pair(cg, orc, gg, 4, start=4)
+    assert relmax(Vg, Vo) < V_TOL and np.max(np.abs(Ug - Uo)) < U_TOL
+
+
 def test_lq_game_matches_separable_oracle(cg, orc):
     # the LQ game in the general form must reproduce the separable oracle
     g = W.make_game(3, 9, seed=8, per_player=True, Nu=6)
