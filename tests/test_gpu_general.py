@@ -93,8 +93,8 @@ def test_largest_sizes(cg, orc):
     (4, (3, 4, 3, 4), (8, 5, 7, 6)),
 ])
 def test_large_control_grids(cg, orc, d, n_p, n_u):
-    # control grids whose coefficients do not fit the LDS-staged Step 1
-    # (more than 64 KiB per node): the streaming kernel runs instead
+    # large control grids (U_P in the thousands): 16-entry register tiles,
+    # many outer indices per lane and several load batches per pair
     gg = W.general_game(d, n_p, n_u, seed=35)
     say(f"  general d={d} n_p={n_p} n_u={n_u} (U_P = {int(np.prod(n_u))})")
     Vg, Ug, rg, Vo, Uo, ro = _run_pair(cg, orc, gg, 4, start=4)
