@@ -278,12 +278,13 @@ int cg_simulate(cg_game *game, const double *p0_dev, int32_t n_paths, int32_t n_
                 double *controls_dev);
 
 /* Timing of the contraction kernel (the kernel that carries the mode-n
- * contractions).  With enable != 0, every later step records a pair of
- * HIP events on the game's stream around that kernel's launch.  If kernel_ms
- * or launches is not NULL the call first synchronises the stream and
- * returns the summed elapsed time and the number of timed launches since the
- * previous cg_profile call; the record is then cleared.  Costs one event
- * pair per step while enabled. */
+ * contractions).  With enable = k >= 1, every k-th later step (the first,
+ * then every k-th) records a pair of HIP events on the game's stream around
+ * that kernel's launch; enable = 0 stops timing.  If kernel_ms or launches
+ * is not NULL the call first synchronises the stream and returns the summed
+ * elapsed time and the number of timed launches since the previous
+ * cg_profile call; the record is then cleared.  Costs one event pair per
+ * timed step.  CG_EINVAL for enable < 0. */
 int cg_profile(cg_game *game, int enable, double *kernel_ms, int64_t *launches);
 
 /* Tile shapes of the game's contraction kernel: rb row blocks of 16 nodes per

@@ -204,11 +204,12 @@ class ChebGame:
         _check(lib().cg_set_state(self.handle, C.c_void_p(V.data_ptr()),
                                   C.c_void_p(U.data_ptr()) if U is not None else None))
 
-    def profile(self, enable: bool = True) -> Tuple[float, int]:
-        """(summed ms, launches) of the contraction kernel since the last call; (re)arms timing."""
+    def profile(self, enable: bool = True, every: int = 1) -> Tuple[float, int]:
+        """(summed ms, launches) of the contraction kernel since the last call;
+        (re)arms timing of every `every`-th iteration's launch (off if not enable)."""
         ms = C.c_double()
         n = C.c_int64()
-        _check(lib().cg_profile(self.handle, 1 if enable else 0, C.byref(ms), C.byref(n)))
+        _check(lib().cg_profile(self.handle, int(every) if enable else 0, C.byref(ms), C.byref(n)))
         return ms.value, n.value
 
     def simulate(self, p0, steps: int, with_controls: bool = True):

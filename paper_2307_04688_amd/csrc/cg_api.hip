@@ -177,6 +177,8 @@ struct cg_game {
     Inst entry;         // host copy of the one-entry device table
     long long launched; // iterations queued (including no-ops after convergence)
     bool prof;                     // record events around the contraction kernel
+    int prof_period;               // ... of every prof_period-th iteration
+    long long prof_seen;           // iterations queued since profiling was enabled
     std::vector<hipEvent_t> evs;   // pairs (begin, end), one pair per profiled launch
     size_t ev_used;
     ~cg_game()
@@ -299,7 +301,7 @@ int queue_steps(cg_game *g, int n)
 {
     for (int s = 0; s < n; ++s) {
         StepBuffers b = g->b;
-        if (g->prof) {
+        if (g->prof && (g->prof_seen++ % g->prof_period) == 0) {
             if (g->ev_used + 2 > g->evs.size()) {
                 for (int k = 0; k < 256; ++k) {
                     hipEvent_t e;
@@ -424,6 +426,8 @@ int cg_init_game(const cg_game_desc *g, int precision, void *ws_dev, size_t ws_b
     hi.E = b.E;
     hi.blk = b.blk;
     G->prof = false;
+    G->prof_period = 1;
+    G->prof_seen = 0;
     G->ev_used = 0;
 
     hipError_t e = hipMemcpyAsync(G->ws + L.gc, &hc, sizeof hc, hipMemcpyHostToDevice, G->stream);
@@ -609,7 +613,10 @@ int cg_profile(cg_game *g, int enable, double *kernel_ms, int64_t *launches)
         if (kernel_ms) *kernel_ms = tot;
         if (launches) *launches = (int64_t)(g->ev_used / 2);
     }
+    if (enable < 0) return fail(CG_EINVAL, "enable < 0");
     g->prof = enable != 0;
+    g->prof_period = enable > 0 ? enable : 1;
+    g->prof_seen = 0;
     g->ev_used = 0;
     return CG_OK;
 }

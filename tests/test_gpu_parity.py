@@ -380,3 +380,22 @@ def test_invalid_arguments_raise(cg):
     assert ei.value.code == cg.EINVAL
     with pytest.raises(cg.ChebGameError):
         cg.chebyshev_transform(dev(np.zeros((40, 4))))
+
+
+def test_profile_sampling(cg):
+    # every k-th iteration's contraction launch is timed (the first, then every k-th)
+    G = _gpu_game(cg, W.make_game(2, 8, seed=1))
+    G.profile(True, every=4)
+    G.step(10)
+    G.step(10)
+    ms, n = G.profile(False)
+    assert n == 5 and ms > 0.0
+    G.profile(True)
+    G.step(3)
+    ms, n = G.profile(False)
+    assert n == 3 and ms > 0.0
+    G.step(2)
+    assert G.profile(False) == (0.0, 0)
+    with pytest.raises(cg.ChebGameError) as ei:
+        G.profile(True, every=-1)
+    assert ei.value.code == cg.EINVAL
