@@ -178,17 +178,32 @@ def run_batch(cg, W, torch, steps: int, warmup: int, count: int = 256, time_step
             "instances_rel_V_above_1e-8": int(np.sum(np.array(errs) > 1e-8))}
 
 
-def run_warm(cg, W, torch, n_train: int = 4096, n_test: int = 16, N: int = 24, train_tol: float = 1e-7,
-             tol: float = 1e-8, max_steps: int = 40000, train_N: int = 12, train_steps: int = 40000):
+# A game whose residual has not fallen by 10 % over STALL_WINDOW iterations
+# (and is still far above the tolerance) has stopped contracting: the
+# iteration should shrink it by (1 - rho h)^2000 <= e^-1 over such a window.
+# Both sides of the warm-start comparison give up on such games.
+STALL_WINDOW = 2000
+
+
+def stalled(r, r_prev, tol):
+    return r > 0.9 * r_prev and r > 100.0 * tol
+
+
+def run_warm(cg, W, torch, n_train: int = 4096, n_test: int = 64, N: int = 24, train_tol: float = 1e-7,
+             tol: float = 1e-8, max_steps: int = 100000, train_N: int = 12, train_steps: int = 40000,
+             slots: int = 32, chunk: int = 500):
     """Learned warm start on d=3 games (seed 5): the network is trained on
     `n_train` games solved by the method (batched, FP32 MFMA + FP64
     correction, to residual `train_tol`) on a train_N grid (the network takes
     node coordinates, so it is then evaluated at the held-out games' N-grid
     nodes), then `n_test` held-out games are
     solved to residual `tol` (a) plainly: FP64, one at a time, from zero, and
-    (b) in the chosen form: FP32 MFMA + FP64 correction, batched, from the
-    network's start, with the plain zero start as fallback for any game that
-    does not converge."""
+    (b) in the chosen form: FP32 MFMA + FP64 correction, from the network's
+    start, batched as a stream through `slots` batch slots (a finished game's
+    slot takes the next game), with the plain zero start as fallback for any
+    game whose warm start or warm iteration is not finite.  The iteration contracts at
+    rate 1 - rho h, so a game with rho near the bottom of its range (0.05)
+    needs ~37 000 iterations to 1e-8: max_steps leaves room for it."""
     import numpy as np
     log = lambda *a: print("bench:", *a, file=sys.stderr, flush=True)
     # the network takes node coordinates, so its training games may use a coarser grid
@@ -197,7 +212,7 @@ def run_warm(cg, W, torch, n_train: int = 4096, n_test: int = 16, N: int = 24, t
     t0 = time.perf_counter()
     hs = [cg.ChebGame(g, cg.FP32_CORR) for g in train]
     B = cg.ChebBatch(hs)
-    for chunk in range(max_steps // 2000):
+    for chunk in range(40000 // 2000):
         _, _, res = B.solve(2000, train_tol)
         done = ~np.isfinite(res) | (res < train_tol)
         log(f"training data: {2000 * (chunk + 1)} iterations, {int(done.sum())}/{n_train} games done")
@@ -229,40 +244,108 @@ def run_warm(cg, W, torch, n_train: int = 4096, n_test: int = 16, N: int = 24, t
     t0 = time.perf_counter()
     for g in test:
         h = cg.ChebGame(g, cg.FP64)
-        try:
-            rc, n, r = h.solve(max_steps, tol)
-            plain_ok.append(rc == cg.OK)
-        except cg.ChebGameError:
-            plain_ok.append(False)
-            n = max_steps
+        n, ok, r_prev = 0, False, float("inf")
+        while n < max_steps:
+            try:
+                rc, m, r = h.solve(STALL_WINDOW, tol)
+            except cg.ChebGameError:      # diverged
+                break
+            n += m
+            if rc == cg.OK:
+                ok = True
+                break
+            if stalled(r, r_prev, tol):
+                break
+            r_prev = r
+        plain_ok.append(ok)
         plain_it.append(n)
         log(f"plain solve {len(plain_it)}/{n_test}: {n} iterations")
         Vref.append(h.get_state()[0] if plain_ok[-1] else None)
         h.destroy()
     torch.cuda.synchronize()
     t_plain = time.perf_counter() - t0
-    # (b) chosen form: warm start, mixed precision, batched; fallback to zero
+    # (b) chosen form: warm start, mixed precision, batched as a stream: up to
+    # `slots` games iterate together and a finished game's slot takes the next
+    # held-out game in place (cg_reset_game), so no game waits for the slowest
+    # one.  The stream is ordered longest first (the iteration contracts at
+    # rate 1 - rho h, so the expected count grows like 1 / rho), and once the
+    # stream is empty the batch is rebuilt over the games still running
+    # whenever they fill half of it (finished games' blocks still cost a
+    # launch slot).  A game whose warm start or warm iteration is not finite
+    # restarts from the zero start in its slot.
     t0 = time.perf_counter()
-    hw = [cg.ChebGame(g, cg.FP32_CORR) for g in test]
-    bad = [net.warm_start(h, W.theta_features(g), 1.0 / g.rho) for g, h in zip(test, hw)]
-    _, wsteps, wres = cg.ChebBatch(hw).solve(max_steps, tol)
-    fell = []
-    for k, (g, h) in enumerate(zip(test, hw)):
-        if not (np.isfinite(wres[k]) and wres[k] < tol):
-            h.reset()
-            try:
-                _, n, r = h.solve(max_steps, tol)
-            except cg.ChebGameError:
-                n, r = max_steps, float("nan")
-            wsteps[k] += n
-            wres[k] = r
-            fell.append(k)
+    order = sorted(range(n_test), key=lambda k: test[k].rho)
+    K = min(n_test, slots)
+    hw = [cg.ChebGame(test[order[s_]], cg.FP32_CORR) for s_ in range(K)]
+    slot_game = [order[s_] for s_ in range(K)]
+    wsteps = np.zeros(n_test, dtype=np.int64)
+    wres = np.full(n_test, np.nan)
+    Vwarm = [None] * n_test
+    fell = set()
+
+    def warm(s, k):
+        if net.warm_start(hw[s], W.theta_features(test[k]), 1.0 / test[k].rho):
+            fell.add(k)
+            hw[s].reinit(test[k])
+
+    for s_ in range(K):
+        warm(s_, slot_game[s_])
+    live = list(range(K))      # slots of the current batch
+    Bw = cg.ChebBatch([hw[s_] for s_ in live])
+    nxt = K
+    t_in_solve, n_calls, batch_iters = 0.0, 0, 0
+    since = np.zeros(n_test, dtype=np.int64)         # iterations since the last stall check
+    r_mark = np.full(n_test, np.inf)                 # residual at that check
+    while live:
+        tc = time.perf_counter()
+        _, steps, res = Bw.solve(chunk, tol)
+        t_in_solve += time.perf_counter() - tc
+        n_calls += 1
+        batch_iters += int(steps.max())
+        for pos, s_ in enumerate(live):
+            k = slot_game[s_]
+            if k < 0:
+                continue
+            wsteps[k] += steps[pos]
+            finished = False
+            if np.isfinite(res[pos]) and res[pos] < tol:
+                wres[k] = res[pos]
+                Vwarm[k] = hw[s_].get_state()[0].clone()
+                finished = True
+            elif not np.isfinite(res[pos]) and k not in fell:
+                fell.add(k)
+                hw[s_].reinit(test[k])      # zero start in the same slot
+                since[k], r_mark[k] = 0, np.inf
+            elif not np.isfinite(res[pos]) or wsteps[k] >= max_steps:
+                finished = True             # diverged again, or out of iterations
+            else:
+                since[k] += steps[pos]
+                if since[k] >= STALL_WINDOW:
+                    if stalled(res[pos], r_mark[k], tol):
+                        finished = True     # the iteration stopped contracting
+                    r_mark[k], since[k] = res[pos], 0
+            if finished:
+                if nxt < n_test:
+                    k2 = order[nxt]
+                    nxt += 1
+                    hw[s_].reinit(test[k2])
+                    slot_game[s_] = k2
+                    warm(s_, k2)
+                else:
+                    slot_game[s_] = -1
+        running = [s_ for s_ in live if slot_game[s_] >= 0]
+        if not running:
+            break
+        if nxt >= n_test and 2 * len(running) <= len(live):
+            Bw.destroy()
+            live = running
+            Bw = cg.ChebBatch([hw[s_] for s_ in live])
     torch.cuda.synchronize()
     t_warm = time.perf_counter() - t0
     errs = []
-    for k, h in enumerate(hw):
-        if Vref[k] is not None and np.isfinite(wres[k]) and wres[k] < tol:
-            V = h.get_state()[0]
+    for k in range(n_test):
+        if Vref[k] is not None and Vwarm[k] is not None:
+            V = Vwarm[k]
             errs.append((torch.max(torch.abs(V - Vref[k])) / torch.max(torch.abs(Vref[k]))).item())
     both = [k for k in range(n_test) if plain_ok[k] and np.isfinite(wres[k]) and wres[k] < tol]
     pi = np.array([plain_it[k] for k in both])
@@ -280,7 +363,9 @@ def run_warm(cg, W, torch, n_train: int = 4096, n_test: int = 16, N: int = 24, t
             "iteration_ratio": float(wi.mean() / pi.mean()) if len(pi) else None,
             "plain_fp64_one_at_a_time_solves_per_s": n_test / t_plain,
             "chosen_mixed_batched_warm_solves_per_s": n_test / t_warm,
-            "speedup": t_plain / t_warm, "fallbacks": len(fell) + int(sum(bad)),
+            "speedup": t_plain / t_warm, "fallbacks": len(fell), "stream_slots": K,
+            "stream_time_in_batch_solves_s": t_in_solve, "stream_batch_solve_calls": n_calls,
+            "stream_batch_iterations": batch_iters, "stream_total_s": t_warm,
             "max_rel_V_vs_plain": max(errs) if errs else None}
 
 
@@ -474,6 +559,7 @@ def main():
     ap.add_argument("--warm-train", type=int, default=4096, help="training games of the warm workload")
     ap.add_argument("--warm-train-n", type=int, default=12, help="their nodes per dimension (0: same as held-out)")
     ap.add_argument("--warm-steps", type=int, default=40000, help="Adam steps of the warm-start training")
+    ap.add_argument("--warm-test", type=int, default=64, help="held-out games of the warm workload")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for scaling rocprof byte counters)")
     args = ap.parse_args()
@@ -506,7 +592,8 @@ def main():
               flush=True)
         return
     if args.workload == "warm":
-        print(json.dumps(run_warm(cg, W, torch, n_train=args.warm_train, train_N=args.warm_train_n,
+        print(json.dumps(run_warm(cg, W, torch, n_train=args.warm_train, n_test=args.warm_test,
+                                  train_N=args.warm_train_n,
                                   train_steps=args.warm_steps)), flush=True)
         return
     if args.workload == "c3":

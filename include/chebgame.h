@@ -111,6 +111,15 @@ int cg_init_game(const cg_game_desc *desc, int precision, void *ws_dev, size_t w
 /* Releases the handle (not the workspace).  NULL is accepted. */
 int cg_destroy(cg_game *game);
 
+/* Re-initialises an existing game in place with another description of the
+ * same d, n_nodes and number of control nodes (its precision is kept): the
+ * constants of Step 0 are rebuilt and V^{[0]} = 0, u^{[0]} = A, the iteration
+ * count and the convergence test are reset.  The workspace layout does not
+ * change, so a batch that holds the game stays valid: a finished game's slot
+ * can take the next game of a stream.  Synchronises the game's stream.
+ * Errors: CG_EINVAL (invalid or differently sized description), CG_EDEVICE. */
+int cg_reset_game(cg_game *game, const cg_game_desc *desc);
+
 /* Algorithm Cnv (Section 3.1, eq. (forcoef) along every mode): coefficient
  * tensors of 'batch' value tensors of shape n[0] x ... x n[d-1], stored one
  * after the other in vals_dev; coef_dev receives them in the same layout and

@@ -69,6 +69,7 @@ def lib() -> C.CDLL:
     L.cg_workspace_bytes.argtypes = [C.POINTER(GameDesc), C.c_int]
     L.cg_init_game.argtypes = [C.POINTER(GameDesc), C.c_int, vp, C.c_size_t, vp, C.POINTER(vp)]
     L.cg_destroy.argtypes = [vp]
+    L.cg_reset_game.argtypes = [vp, C.POINTER(GameDesc)]
     L.cg_chebyshev_transform.argtypes = [C.c_int, ip, vp, vp, C.c_int64, vp]
     L.cg_eval_workspace_bytes.restype = C.c_size_t
     L.cg_eval_workspace_bytes.argtypes = [C.c_int, ip, C.c_int]
@@ -227,6 +228,12 @@ class ChebGame:
     def set_tiles(self, rb: int = 2, ocb: int = 1):
         """Contraction tile shapes: row blocks of 16 per wave, outer values per slab."""
         _check(lib().cg_set_tiles(self.handle, rb, ocb))
+
+    def reinit(self, game):
+        """This handle (and its workspace) re-initialised for another game of
+        the same d, N and control nodes: constants rebuilt, V = 0, u = A."""
+        keep: list = []
+        _check(lib().cg_reset_game(self.handle, C.byref(_desc(game, keep))))
 
     def reset(self):
         """Back to the zero terminal value V = 0, u = A (iteration count kept)."""

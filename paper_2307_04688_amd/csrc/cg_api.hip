@@ -320,6 +320,38 @@ int queue_steps(cg_game *g, int n)
     return CG_OK;
 }
 
+// Constants of a game description (Step 0: grids, matrices, parameters).
+void build_consts(const cg_game_desc *g, GameConst &hc)
+{
+    memset(&hc, 0, sizeof hc);
+    const int d = g->d, N = g->n_nodes, Nu = g->n_unodes ? g->n_unodes : g->n_nodes;
+    hc.d = d;
+    hc.N = N;
+    hc.Nu = Nu;
+    dims(g, hc.N4, hc.NC, hc.K, hc.NN);
+    hc.h = g->h;
+    hc.rho = g->rho;
+    hc.pmax = g->p_max;
+    hc.umax = g->u_max;
+    hc.delta = 1.0 - g->rho * g->h;
+    for (int i = 0; i < d; ++i) {
+        const double mi = g->m ? g->m[i] : 1.0;
+        for (int j = 0; j < d; ++j) hc.M[i * d + j] = g->K[i * d + j] / mi - (i == j ? g->c[i] : 0.0);
+        hc.beta[i] = g->beta[i];
+        hc.A[i] = g->A[i];
+        hc.phi[i] = g->phi[i];
+    }
+    hc.tol = 0.0;
+    for (int k = 0; k < N; ++k) {
+        hc.xnode[k] = cos_pi_frac(k, N - 1);
+        hc.pnode[k] = 0.5 * g->p_max * (hc.xnode[k] + 1.0);
+    }
+    for (int m = 0; m < Nu; ++m) hc.unode[m] = 0.5 * g->u_max * (cos_pi_frac(m, Nu - 1) + 1.0);
+    dct1_matrix(Nu, hc.Du);
+    dct1_matrix(N, hc.Dx);
+    diff_matrix(N, hc.Dx, hc.xnode, hc.Dd);
+}
+
 }  // namespace
 
 extern "C" {
@@ -363,33 +395,7 @@ int cg_init_game(const cg_game_desc *g, int precision, void *ws_dev, size_t ws_b
     cg_game *G = new (std::nothrow) cg_game();
     if (!G) return fail(CG_ENOMEM, "host allocation failed");
     GameConst &hc = G->hc;
-    memset(&hc, 0, sizeof hc);
-    const int d = g->d, N = g->n_nodes, Nu = g->n_unodes ? g->n_unodes : g->n_nodes;
-    hc.d = d;
-    hc.N = N;
-    hc.Nu = Nu;
-    dims(g, hc.N4, hc.NC, hc.K, hc.NN);
-    hc.h = g->h;
-    hc.rho = g->rho;
-    hc.pmax = g->p_max;
-    hc.umax = g->u_max;
-    hc.delta = 1.0 - g->rho * g->h;
-    for (int i = 0; i < d; ++i) {
-        const double mi = g->m ? g->m[i] : 1.0;
-        for (int j = 0; j < d; ++j) hc.M[i * d + j] = g->K[i * d + j] / mi - (i == j ? g->c[i] : 0.0);
-        hc.beta[i] = g->beta[i];
-        hc.A[i] = g->A[i];
-        hc.phi[i] = g->phi[i];
-    }
-    hc.tol = 0.0;
-    for (int k = 0; k < N; ++k) {
-        hc.xnode[k] = cos_pi_frac(k, N - 1);
-        hc.pnode[k] = 0.5 * g->p_max * (hc.xnode[k] + 1.0);
-    }
-    for (int m = 0; m < Nu; ++m) hc.unode[m] = 0.5 * g->u_max * (cos_pi_frac(m, Nu - 1) + 1.0);
-    dct1_matrix(Nu, hc.Du);
-    dct1_matrix(N, hc.Dx);
-    diff_matrix(N, hc.Dx, hc.xnode, hc.Dd);
+    build_consts(g, hc);
 
     G->L = L;
     G->ws = (char *)ws_dev;
@@ -464,6 +470,27 @@ int cg_init_game(const cg_game_desc *g, int precision, void *ws_dev, size_t ws_b
 int cg_destroy(cg_game *game)
 {
     delete game;
+    return CG_OK;
+}
+
+int cg_reset_game(cg_game *G, const cg_game_desc *g)
+{
+    if (!G) return fail(CG_EINVAL, "game is NULL");
+    int rc = validate(g, G->precision);
+    if (rc != CG_OK) return rc;
+    const int Nu = g->n_unodes ? g->n_unodes : g->n_nodes;
+    if (g->d != G->hc.d || g->n_nodes != G->hc.N || Nu != G->hc.Nu)
+        return fail(CG_EINVAL, "reset needs the same d, n_nodes and control nodes (%d, %d, %d)", G->hc.d, G->hc.N,
+                    G->hc.Nu);
+    GameConst hc;
+    build_consts(g, hc);
+    hc.tol = 0.0;
+    HIP_TRY(hipMemcpyAsync(G->ws + G->L.gc, &hc, sizeof hc, hipMemcpyHostToDevice, G->stream),
+            "hipMemcpyAsync(constants)");
+    hipLaunchKernelGGL(k_fill_state, dim3(256), dim3(256), 0, G->stream, G->b.V, G->b.U, G->b.gc, G->b.status);
+    HIP_TRY(hipGetLastError(), "reset launch");
+    HIP_TRY(hipStreamSynchronize(G->stream), "hipStreamSynchronize");  // hc must outlive the copy
+    G->hc = hc;
     return CG_OK;
 }
 

@@ -142,3 +142,29 @@ def test_batch_mixed_dimensions_and_fit_paths(cg):
         single.solve(20)
         assert torch.equal(single.get_state()[0], h.get_state()[0]), (g.d, g.N, g.Nu)
         assert torch.equal(single.get_state()[1], h.get_state()[1]), (g.d, g.N, g.Nu)
+
+
+@pytest.mark.parametrize("prec", ["FP64", "FP32_CORR"])
+def test_reinit_slot_streams_games(cg, prec):
+    # a batch slot re-initialised with the next game of a stream (cg_reset_game)
+    # solves it exactly as a fresh handle does; the batch's graph stays valid
+    p = getattr(cg, prec)
+    first = [W.make_game(3, 9, seed=21, instance=i) for i in range(3)]
+    nxt = [W.make_game(3, 9, seed=21, instance=10 + i) for i in range(3)]
+    handles = [cg.ChebGame(g, p) for g in first]
+    B = cg.ChebBatch(handles)
+    B.solve(12)
+    handles[1].reinit(nxt[1])
+    handles[2].reinit(nxt[2])
+    rc, steps, res = B.solve(12)
+    assert rc == cg.OK and np.all(steps == 12)
+    for slot, g in ((0, None), (1, nxt[1]), (2, nxt[2])):
+        ref = cg.ChebGame(g if g is not None else first[0], p)
+        ref.solve(24 if g is None else 12)
+        Vr, Ur, _ = ref.get_state()
+        Vb, Ub, nb = handles[slot].get_state()
+        assert torch.equal(Vr, Vb) and torch.equal(Ur, Ub), slot
+        assert nb == (24 if g is None else 12)
+    with pytest.raises(cg.ChebGameError) as ei:
+        handles[0].reinit(W.make_game(3, 8, seed=21))
+    assert ei.value.code == cg.EINVAL
