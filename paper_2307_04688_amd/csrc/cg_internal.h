@@ -128,8 +128,11 @@ struct StepBuffers {
     int ocb;                      // outer-mode values per LDS slab in the contraction (1 or 2)
 };
 hipError_t launch_transform_game(const GameConst &hc, const StepBuffers &b, hipStream_t s);
+// The passes after the first (modes 0..d-3 and the packed operand; none for d = 2).
+hipError_t launch_transform_rest(const GameConst &hc, const StepBuffers &b, hipStream_t s);
+// First transform pass and Taylor tensors in one launch (mixed path).
+hipError_t launch_tf_taylor(const GameConst &hc, const StepBuffers &b, hipStream_t s);
 hipError_t launch_step(const GameConst &hc, const StepBuffers &b, hipStream_t s);
-hipError_t launch_taylor(const GameConst &hc, const StepBuffers &b, hipStream_t s);
 hipError_t launch_contract_corr(const GameConst &hc, const StepBuffers &b, hipStream_t s);
 
 hipError_t launch_eval(int d, const int *n, const double *coef, const double *x, long long npts,

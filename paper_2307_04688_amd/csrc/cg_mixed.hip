@@ -23,6 +23,7 @@
 // where Pb_S is the product of Tb and FO_S its first-order part, so each
 // K element costs three multiply-adds once the outer modes are combined.
 #include "cg_line.h"
+#include "cg_tf.h"
 
 namespace cg {
 
@@ -34,18 +35,15 @@ namespace cg {
 // LDS, G = V Dx^T along mode i, then Dd G along l; the s = 0 planes also
 // write slot 0.
 template <int NP>
-__global__ __launch_bounds__(256) void k_taylor(const Inst *__restrict__ tab, int bpi)
+__device__ __forceinline__ void taylor_block(const Inst *__restrict__ tab, int bpi, int bid, double *sm)
 {
-    const InstView I = inst_view(tab, blockIdx.x / bpi);
-    const int blk = blockIdx.x % bpi;
+    const InstView I = inst_view(tab, bid / bpi);
+    const int blk = bid % bpi;
     const GameConst *__restrict__ gc = I.gc;
     const GameStatus *st = I.st;
     double *E = I.E;
     constexpr int LD = kMaxN + 1;
-    __shared__ double Dx[kMaxN * LD];
-    __shared__ double Dd[kMaxN * LD];
-    __shared__ double X[kMaxN * LD];
-    __shared__ double Gp[kMaxN * LD];
+    double *Dx = sm, *Dd = sm + kMaxN * LD, *X = sm + 2 * kMaxN * LD, *Gp = sm + 3 * kMaxN * LD;
     if (st->converged) return;
     const int N = gc->N, d = gc->d, NC = gc->NC;
     const long long NN = gc->NN;
@@ -108,15 +106,32 @@ __global__ __launch_bounds__(256) void k_taylor(const Inst *__restrict__ tab, in
     }
 }
 
-hipError_t launch_taylor(const GameConst &hc, const StepBuffers &b, hipStream_t s)
+// The first transform pass and the Taylor tensors in one launch: both read
+// only V^{[r]} and each alone fills few CUs (d N slices; d (d-1) N^(d-2)
+// planes).  Blocks [0, count bpi_tf) run the transform pass, the rest the
+// Taylor planes.
+template <int NP>
+__global__ __launch_bounds__(256) void k_tf_taylor(const Inst *__restrict__ tab, int bpi_tf, int bpi_ty, int n_tf)
+{
+    __shared__ double sm[4 * kMaxN * (kMaxN + 1)];
+    if ((int)blockIdx.x < n_tf)
+        tf_fast_block<NP>(tab, bpi_tf, 1, blockIdx.x, sm);
+    else
+        taylor_block<NP>(tab, bpi_ty, blockIdx.x - n_tf, sm);
+}
+
+hipError_t launch_tf_taylor(const GameConst &hc, const StepBuffers &b, hipStream_t s)
 {
     int nf = 1;
     for (int q = 0; q < hc.d - 2; ++q) nf *= hc.N;
-    const int bpi = hc.d * (hc.d - 1) * nf;
+    const int bpi_ty = hc.d * (hc.d - 1) * nf;
+    const int bpi_tf = (int)(hc.NN / ((long long)hc.N * hc.N)) * hc.d;
+    const int n_tf = bpi_tf * b.count;
+    const unsigned grid = (unsigned)(n_tf + bpi_ty * b.count);
     if (hc.N <= 16)
-        hipLaunchKernelGGL(k_taylor<16>, dim3((unsigned)(bpi * b.count)), dim3(256), 0, s, b.tab, bpi);
+        hipLaunchKernelGGL(k_tf_taylor<16>, dim3(grid), dim3(256), 0, s, b.tab, bpi_tf, bpi_ty, n_tf);
     else
-        hipLaunchKernelGGL(k_taylor<32>, dim3((unsigned)(bpi * b.count)), dim3(256), 0, s, b.tab, bpi);
+        hipLaunchKernelGGL(k_tf_taylor<32>, dim3(grid), dim3(256), 0, s, b.tab, bpi_tf, bpi_ty, n_tf);
     return hipGetLastError();
 }
 

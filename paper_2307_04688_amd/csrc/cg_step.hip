@@ -369,10 +369,6 @@ static hipError_t launch_step_dn(const GameConst &hc, const StepBuffers &b, hipS
     constexpr int NC = N4 <= 16 ? 16 : 32;
     const int NN = (int)hc.NN;
     hipError_t e;
-    if (b.precision == CG_FP32_CORR) {
-        e = launch_taylor(hc, b, s);
-        if (e != hipSuccess) return e;
-    }
     if (b.ev_begin) {
         e = hipEventRecord(b.ev_begin, s);
         if (e != hipSuccess) return e;
@@ -427,8 +423,10 @@ static hipError_t launch_step_d(const GameConst &hc, const StepBuffers &b, hipSt
 
 hipError_t launch_step(const GameConst &hc, const StepBuffers &b, hipStream_t s)
 {
-    // 1. coefficients of every V_i (Algorithm Cnv) into the packed operand
-    hipError_t e = launch_transform_game(hc, b, s);
+    // 1. coefficients of every V_i (Algorithm Cnv) into the packed operand;
+    //    the mixed path computes its Taylor tensors in the first pass's launch
+    hipError_t e = b.precision == CG_FP32_CORR ? launch_tf_taylor(hc, b, s) : launch_transform_game(hc, b, s);
+    if (e == hipSuccess && b.precision == CG_FP32_CORR) e = launch_transform_rest(hc, b, s);
     if (e != hipSuccess) return e;
     // 2. contraction (MFMA), then line fit + argmax + residual + bookkeeping
     switch (hc.d) {

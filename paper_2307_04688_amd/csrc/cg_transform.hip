@@ -8,7 +8,7 @@
 // writes one coefficient per thread, so it may run in place; the N x N
 // matrix is built in LDS by each block.  The transform is a small share of a
 // step (2 d N^(d+1) flops per tensor against 2 N^(2d) for the contraction).
-#include "cg_internal.h"
+#include "cg_tf.h"
 
 namespace cg {
 
@@ -90,70 +90,11 @@ hipError_t run_transform(int d, const int *n, const double *vals, double *coef, 
 //     Bp[i][kidx][col], col = k_i, kidx enumerating the other modes in
 //     increasing order with the last of them padded to N4 (padding entries are
 //     zero from initialisation and never written).
-__device__ __forceinline__ long long packed_index(const GameConst *__restrict__ gc, int i, const int *dig)
-{
-    const int d = gc->d, N = gc->N;
-    const int lastother = (i == d - 1) ? d - 2 : d - 1;
-    int col = 0, kl = 0, kout = 0;
-    for (int l = 0; l < d; ++l) {
-        if (l == i) col = dig[l];
-        else if (l == lastother) kl = dig[l];
-        else kout = kout * N + dig[l];
-    }
-    return ((long long)i * gc->K + (long long)kout * gc->N4 + kl) * gc->NC + col;
-}
-
 template <int NP>
 __global__ __launch_bounds__(256) void k_tf_fast(const Inst *__restrict__ tab, int bpi, int mixed)
 {
-    const InstView I = inst_view(tab, blockIdx.x / bpi);
-    const int blk = blockIdx.x % bpi;
-    const GameConst *__restrict__ gc = I.gc;
-    const GameStatus *st = I.st;
-    const double *Vbuf = I.V;
-    double *out = I.tmp, *Bp = I.Bp;
-    float *Bp32 = mixed ? I.Bp32 : nullptr;
-    constexpr int LD = kMaxN + 1;  // odd stride: column reads hit distinct banks
-    __shared__ double Dm[kMaxN * LD];
-    __shared__ double X[kMaxN * LD];
-    __shared__ double Y[kMaxN * LD];
-    if (st->converged) return;
-    const int N = gc->N, d = gc->d, NN2 = N * N;
-    const long long NN = gc->NN;
-    const int nslice = (int)(NN / NN2);
-    const int i = blk / nslice, sl = blk % nslice;
-    const double *src = Vbuf + (long long)st->cur * d * NN + (long long)i * NN + (long long)sl * NN2;
-    for (int e = threadIdx.x; e < NP * NP; e += blockDim.x) {  // zero beyond N
-        const int r = e / NP, c = e % NP;
-        const bool in = r < N && c < N;
-        Dm[r * LD + c] = in ? gc->Dx[r * kMaxN + c] : 0.0;
-        X[r * LD + c] = in ? src[r * N + c] : 0.0;
-    }
-    __syncthreads();
-    // Y = D X (mode d-2), then Z = Y D^T (mode d-1), on FP64 MFMA
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int r16 = lane & 15, kq = lane >> 4;
-    f64x4 acc;
-    int ti, tj;
-    if (plane_mfma<NP, LD, false, false>(Dm, X, wave, lane, acc, ti, tj)) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) Y[(ti * 16 + kq + 4 * v) * LD + tj * 16 + r16] = acc[v];
-    }
-    __syncthreads();
-    if (plane_mfma<NP, LD, false, true>(Y, Dm, wave, lane, acc, ti, tj)) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int r = ti * 16 + kq + 4 * v, c = tj * 16 + r16;
-            if (r >= N || c >= N) continue;
-            if (d > 2) {
-                out[(long long)i * NN + (long long)sl * NN2 + r * N + c] = acc[v];
-            } else {
-                int dig[kMaxD] = {r, c, 0, 0};
-                const long long o = packed_index(gc, i, dig);
-                if (Bp32) Bp32[o] = (float)acc[v]; else Bp[o] = acc[v];
-            }
-        }
-    }
+    __shared__ double sm[3 * kMaxN * (kMaxN + 1)];
+    tf_fast_block<NP>(tab, bpi, mixed, blockIdx.x, sm);
 }
 
 // Tile of the outer modes: X[f][q], f over the N^(d-2) outer positions,
@@ -270,7 +211,16 @@ hipError_t launch_transform_game(const GameConst &hc, const StepBuffers &b, hipS
     else
         hipLaunchKernelGGL(k_tf_fast<32>, dim3((unsigned)(bpi1 * b.count)), dim3(256), 0, s, b.tab, bpi1, mixed);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess || d == 2) return e;
+    if (e != hipSuccess) return e;
+    return launch_transform_rest(hc, b, s);
+}
+
+hipError_t launch_transform_rest(const GameConst &hc, const StepBuffers &b, hipStream_t s)
+{
+    const int N = hc.N, d = hc.d;
+    const int mixed = b.precision == CG_FP32_CORR;
+    const long long nslice = hc.NN / (N * N);
+    if (d == 2) return hipSuccess;
     if (d == 3) {
         const int NP = N <= 16 ? 16 : 32;
         const int bpi3 = d * ((N * N + NP - 1) / NP);
