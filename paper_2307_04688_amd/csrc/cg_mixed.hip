@@ -381,8 +381,9 @@ __global__ __launch_bounds__(256) void k_contract_corr(const Inst *__restrict__ 
 #pragma unroll
             for (int c = 0; c < NCB; ++c) bf[t][c] = cb[(4 * t + kq) * LDB + c * 16 + r16];
         // keep the reads ahead of the MFMAs (the scheduler would otherwise sink
-        // each read to just before its MFMA and expose its latency)
-        __builtin_amdgcn_sched_barrier(0);
+        // each read to just before its MFMA and expose its latency); measured
+        // faster at d = 3 only
+        if constexpr (D == 3) __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int t = 0; t < N4 / 4; ++t) {
 #pragma unroll
