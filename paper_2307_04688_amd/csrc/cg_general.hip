@@ -10,11 +10,13 @@
 //               (the per-node evaluation of Section 3.3), leaving series in
 //               u_i that are summed at player i's control nodes; the result
 //               gives the update points p_j + h g(p_j, [u_m, u_{-i}]) and the
-//               payoff samples.  One wave per (node, player); a block holds
-//               the d waves of one node, so the node's coefficients are read
-//               from HBM once and shared through the caches.
-//   evaluation  Step 2: V_i^{[r]} at every update point: the scattered-point
-//               evaluation (Khatri-Rao GEMM on FP64 MFMA + Clenshaw).
+//               payoff samples.  A 16-lane group per (node, player); a block
+//               holds whole nodes (the coefficients are stored node-major),
+//               so each node's coefficients are read from HBM once and
+//               shared through the caches.
+//   evaluation  Step 2: V_i^{[r]} at every update point, all players in one
+//               launch: the scattered-point evaluation (Khatri-Rao GEMM on
+//               FP64 MFMA + Clenshaw).
 //   line        Steps 3-4: fit of the samples in u (DCT-I), argmax on
 //               [0, u_max], new value and control, per-block residual maxima.
 //   finish      residual, TOL test, status.
