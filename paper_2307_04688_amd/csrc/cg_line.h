@@ -302,11 +302,13 @@ __device__ __forceinline__ void line_compose(const GameConst *__restrict__ gc, i
         const int len = NW - k;              // entries of b_k
 #pragma unroll
         for (int m = 0; m < len; ++m) {
-            double sb;  // coefficient m of 2 c s b_{k+1}
-            if (m == 0) sb = c * B1[1];
-            else if (m == 1) sb = fma(c2, B1[0], c * B1[2]);
-            else sb = c * (B1[m - 1] + (m + 1 < NW ? B1[m + 1] : 0.0));
-            const double t = fma(a2, B1[m], sb) - B0[m];
+            // 2 (a + c s) b_{k+1} - b_{k+2}, coefficient m; the term of c s
+            // b_{k+1} is c (b_{m-1} + b_{m+1}) except at m = 0, 1
+            const double lin = fma(a2, B1[m], -B0[m]);
+            double t;
+            if (m == 0) t = fma(c, B1[1], lin);
+            else if (m == 1) t = fma(c2, B1[0], fma(c, B1[2], lin));
+            else t = fma(c, B1[m - 1] + (m + 1 < NW ? B1[m + 1] : 0.0), lin);
             B0[m] = (m == 0) ? t + w[k] : t;
         }
     }
