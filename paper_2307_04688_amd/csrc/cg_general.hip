@@ -10,10 +10,11 @@
 //               (the per-node evaluation of Section 3.3), leaving series in
 //               u_i that are summed at player i's control nodes; the result
 //               gives the update points p_j + h g(p_j, [u_m, u_{-i}]) and the
-//               payoff samples.  A 16-lane group per (node, player); a block
-//               holds whole nodes (the coefficients are stored node-major),
-//               so each node's coefficients are read from HBM once and
-//               shared through the caches.
+//               payoff samples.  A 16-lane group per (node, player), one
+//               wave per player over four nodes; a block holds whole nodes
+//               (the coefficients are stored node-major), so each node's
+//               coefficients are read from HBM once and shared through the
+//               caches.
 //   evaluation  Step 2: V_i^{[r]} at every update point, all players in one
 //               launch: the scattered-point evaluation (Khatri-Rao GEMM on
 //               FP64 MFMA + Clenshaw).
@@ -114,94 +115,195 @@ __device__ __forceinline__ double row16_sum(double v)
     return v;
 }
 
-// Step 1 for (node, player) pairs: 16 lanes per pair, G pairs per block (G
-// the largest multiple of D that fits 256 threads).  Pair q = blockIdx.x G +
-// group is node j = q / D, player i = q % D, so the D players of a node are
-// groups of one block and share the node's drift tensors (one contiguous
-// block per node in the node-major layout) through the caches.  Each lane contracts a strided share of the
-// outer control indices; the 16 partial sums of every coefficient are then
-// combined within the group (row16_sum).  NUM >= every n_unodes, a multiple
-// of 4 (register arrays stay compile-time sized).
+// Step 1 for the (node, player) pairs of NB = 4 consecutive nodes: wave i of
+// the block serves player i and its four 16-lane groups the four nodes, so
+// the D players of a node share the node's drift coefficients (one
+// contiguous block per node in the node-major layout) through the caches,
+// and every branch on the player is uniform over a wave.  NUM >= every
+// n_unodes, a multiple of 4 (register arrays stay compile-time sized).
+//
+// Players i < D - 1: each lane contracts a strided share of the outer control
+// indices o (the other modes in C order, the last mode fastest, so that
+// neighbouring lanes read neighbouring coefficients) for every coefficient a
+// of the series in u_i; the 16 partial sums of each are combined by
+// row16_sum; one outer index at a time, with at most 128 VGPRs when the
+// (D + 1) NUM accumulators allow it: four waves per SIMD hide more of the
+// load latency than a deeper unroll at three (measured 77.8 against 80.1 us
+// at d = 3, n_u = 8).  Player D - 1, whose mode has stride 1 in a control tensor:
+// lane s n_u + a keeps coefficient a and every S-th index of mode D - 2
+// (S = 16 / n_u slices; with n_u even, two neighbouring coefficients per lane
+// and one 16-byte load), so that the lanes of a group read one contiguous run
+// per load; the S slice sums meet in LDS.
 template <int D, int NUM>
-__global__ __launch_bounds__(256) void k_gen_points(const GenConst *__restrict__ gc,
-                                                    const GenStatus *__restrict__ st,
-                                                    const double *__restrict__ U,
-                                                    const double *__restrict__ cc, double *__restrict__ pts,
-                                                    double *__restrict__ psamp)
+__global__ __launch_bounds__(64 * D) __attribute__((amdgpu_waves_per_eu((D + 1) * NUM <= 32 ? 4 : 1)))
+void k_gen_points(const GenConst *__restrict__ gc, const GenStatus *__restrict__ st, const double *__restrict__ U,
+                  const double *__restrict__ cc, double *__restrict__ pts, double *__restrict__ psamp)
 {
-    constexpr int L = 16, G = (256 / L / D) * D;
-    __shared__ double Tb[G][D][NUM];
-    if (st->converged) return;
-    const int tid = threadIdx.x, grp = tid / L, lane = tid % L;
+    constexpr int L = 16, NB = 4;
+    __shared__ double Tb[NB][D][NUM];
+    __shared__ double Sb[NB][D + 1][2 * L];
+    if (st->converged) return;  // the same for every thread, before any barrier
+    const int tid = threadIdx.x, i = tid / 64, g = (tid % 64) / L, lane = tid % L;
     const long long NP = gc->NP, UP = gc->UP;
-    const long long pair = (long long)blockIdx.x * G + grp;
-    const bool active = pair < NP * D;
-    const long long j = active ? pair / D : 0;
-    const int i = (int)(pair % D);
-    // T_a(y_l) at the node's current controls, y_l = 2 u_l / u_max - 1
-    for (int t = lane; t < D * NUM; t += L) {
-        const int l = t / NUM, a = t % NUM;
-        const double y = 2.0 * U[l * NP + j] / gc->umax - 1.0;
+    const long long j0 = (long long)blockIdx.x * NB;
+    // T_a(y_l) at the nodes' current controls, y_l = 2 u_l / u_max - 1
+    for (int t = tid; t < NB * D * NUM; t += 64 * D) {
+        const int n = t / (D * NUM), l = (t / NUM) % D, a = t % NUM;
+        const long long jn = j0 + n < NP ? j0 + n : NP - 1;
+        const double y = 2.0 * U[l * NP + jn] / gc->umax - 1.0;
         double tm1 = 1.0, t0 = y, ta = a == 0 ? 1.0 : y;
         for (int k = 2; k <= a; ++k) {
             ta = 2.0 * y * t0 - tm1;
             tm1 = t0;
             t0 = ta;
         }
-        Tb[grp][l][a] = ta;
+        Tb[n][l][a] = ta;
     }
     __syncthreads();
-    if (!active) return;  // whole groups only: the shuffles below stay inside a group
-
+    const long long j = j0 + g;
+    const bool active = j < NP;
     const int nui = gc->nu[i];
-    const int si = gc->ustride[i];
-    const int nouter = (int)(UP / nui);
     double acc[D + 1][NUM];
 #pragma unroll
     for (int k = 0; k <= D; ++k)
 #pragma unroll
         for (int a = 0; a < NUM; ++a) acc[k][a] = 0.0;
-    const double *gbase = cc + j * (2 * D) * UP;  // drift component k at + k UP
-    const double *pbase = gbase + (D + i) * UP;    // payoff of player i
-    // The loads of one outer index are issued together: no data-dependent
-    // branch between them (entries a >= nui read a valid address, entry
-    // nui - 1, and are weighted by zero).
+    const double *gbase = cc + (active ? j : 0) * (2 * D) * UP;  // drift component k at + k UP
+    const double *pbase = gbase + (D + i) * UP;                   // payoff of player i
+    if (i < D - 1) {
+        if (active) {
+            const int si = gc->ustride[i];
+            const int nouter = (int)(UP / nui);
+            // The loads of one outer index are issued together: no
+            // data-dependent branch between them (entries a >= nui read a
+            // valid address, entry nui - 1, and are weighted by zero).
+#pragma unroll 1
+            for (int o = lane; o < nouter; o += L) {
+                int rem = o, base = 0;
+                double w = 1.0;
+#pragma unroll
+                for (int l = D - 1; l >= 0; --l) {
+                    if (l == i) continue;
+                    const int a = rem % gc->nu[l];
+                    rem /= gc->nu[l];
+                    base += a * gc->ustride[l];
+                    w *= Tb[g][l][a];
+                }
+                double v[D + 1][NUM];
+#pragma unroll
+                for (int a = 0; a < NUM; ++a) {
+                    const int off = base + (a < nui ? a : nui - 1) * si;
+#pragma unroll
+                    for (int k = 0; k < D; ++k) v[k][a] = gbase[k * UP + off];
+                    v[D][a] = pbase[off];
+                }
+#pragma unroll
+                for (int a = 0; a < NUM; ++a) {
+                    const double wa = a < nui ? w : 0.0;
+#pragma unroll
+                    for (int k = 0; k <= D; ++k) acc[k][a] = fma(v[k][a], wa, acc[k][a]);
+                }
+            }
+#pragma unroll
+            for (int a = 0; a < NUM; ++a) {
+                if (a < nui) {
+#pragma unroll
+                    for (int k = 0; k <= D; ++k) acc[k][a] = row16_sum(acc[k][a]);
+                }
+            }
+        }
+    } else if ((nui & 1) == 0) {
+        // even n_u: lane s (n_u / 2) + c keeps coefficients 2c and 2c + 1
+        // (one 16-byte load per function; S = 32 / n_u slices)
+        const int hw = nui / 2, S = L / hw, a = 2 * (lane % hw), slice = lane / hw;
+        double part[D + 1][2];
+#pragma unroll
+        for (int k = 0; k <= D; ++k) part[k][0] = part[k][1] = 0.0;
+        if (active && slice < S) {
+            const int nin = gc->nu[D - 2];                        // the mode split over slices
+            const int nhi = (int)(UP / ((long long)nin * nui));   // modes 0 .. D-3
+            for (int hi = 0; hi < nhi; ++hi) {
+                int rem = hi;
+                double wh = 1.0;
+#pragma unroll
+                for (int l = D - 3; l >= 0; --l) {
+                    const int al = rem % gc->nu[l];
+                    rem /= gc->nu[l];
+                    wh *= Tb[g][l][al];
+                }
+                const int row = hi * nin;
 #pragma unroll 2
-    for (int o = lane; o < nouter; o += L) {
-        // o enumerates the control modes other than i in C order
-        int rem = o, base = 0;
-        double w = 1.0;
+                for (int b = slice; b < nin; b += S) {
+                    const double w = wh * Tb[g][D - 2][b];
+                    const int off = (row + b) * nui + a;   // even: 16-byte aligned
+                    double2 v[D + 1];
 #pragma unroll
-        for (int l = D - 1; l >= 0; --l) {
-            if (l == i) continue;
-            const int a = rem % gc->nu[l];
-            rem /= gc->nu[l];
-            base += a * gc->ustride[l];
-            w *= Tb[grp][l][a];
+                    for (int k = 0; k < D; ++k) v[k] = *(const double2 *)(gbase + k * UP + off);
+                    v[D] = *(const double2 *)(pbase + off);
+#pragma unroll
+                    for (int k = 0; k <= D; ++k) {
+                        part[k][0] = fma(v[k].x, w, part[k][0]);
+                        part[k][1] = fma(v[k].y, w, part[k][1]);
+                    }
+                }
+            }
         }
-        double v[D + 1][NUM];
+#pragma unroll
+        for (int k = 0; k <= D; ++k) {
+            Sb[g][k][2 * lane] = part[k][0];
+            Sb[g][k][2 * lane + 1] = part[k][1];
+        }
+    } else {
+        const int S = L / nui, a = lane % nui, slice = lane / nui;
+        double part[D + 1];
+#pragma unroll
+        for (int k = 0; k <= D; ++k) part[k] = 0.0;
+        if (active && slice < S) {
+            const int nin = gc->nu[D - 2];                        // the mode split over slices
+            const int nhi = (int)(UP / ((long long)nin * nui));   // modes 0 .. D-3
+            for (int hi = 0; hi < nhi; ++hi) {
+                int rem = hi;
+                double wh = 1.0;
+#pragma unroll
+                for (int l = D - 3; l >= 0; --l) {
+                    const int al = rem % gc->nu[l];
+                    rem /= gc->nu[l];
+                    wh *= Tb[g][l][al];
+                }
+                const int row = hi * nin;
+#pragma unroll 2
+                for (int b = slice; b < nin; b += S) {
+                    const double w = wh * Tb[g][D - 2][b];
+                    const int off = (row + b) * nui + a;
+                    double v[D + 1];
+#pragma unroll
+                    for (int k = 0; k < D; ++k) v[k] = gbase[k * UP + off];
+                    v[D] = pbase[off];
+#pragma unroll
+                    for (int k = 0; k <= D; ++k) part[k] = fma(v[k], w, part[k]);
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k <= D; ++k) Sb[g][k][lane] = part[k];
+    }
+    __syncthreads();
+    if (i == D - 1 && active) {
+        // coefficient a of every series: the slice sums in slice order
+        const int S = (nui & 1) ? L / nui : L / (nui / 2);
 #pragma unroll
         for (int a = 0; a < NUM; ++a) {
-            const int off = base + (a < nui ? a : nui - 1) * si;
+            if (a < nui) {
 #pragma unroll
-            for (int k = 0; k < D; ++k) v[k][a] = gbase[k * UP + off];
-            v[D][a] = pbase[off];
-        }
-#pragma unroll
-        for (int a = 0; a < NUM; ++a) {
-            const double wa = a < nui ? w : 0.0;
-#pragma unroll
-            for (int k = 0; k <= D; ++k) acc[k][a] = fma(v[k][a], wa, acc[k][a]);
+                for (int k = 0; k <= D; ++k) {
+                    double s = Sb[g][k][a];
+                    for (int q = 1; q < S; ++q) s += Sb[g][k][q * nui + a];
+                    acc[k][a] = s;
+                }
+            }
         }
     }
-#pragma unroll
-    for (int a = 0; a < NUM; ++a) {
-        if (a < nui) {
-#pragma unroll
-            for (int k = 0; k <= D; ++k) acc[k][a] = row16_sum(acc[k][a]);
-        }
-    }
-    if (lane < nui) {
+    if (active && lane < nui) {
         // lane m: control node u_m of player i; series in u_i by Clenshaw
         // (entries a >= nui are zero)
         const double t = gc->tnode[i][lane];
@@ -216,8 +318,8 @@ __global__ __launch_bounds__(256) void k_gen_points(const GenConst *__restrict__
         const long long q = gc->off[i] + j * nui + lane;
 #pragma unroll
         for (int l = 0; l < D; ++l) {
-            const double g = clenshaw(acc[l], t);
-            pts[q * D + l] = 2.0 * fma(gc->h, g, p[l]) / gc->pmax - 1.0;
+            const double gl = clenshaw(acc[l], t);
+            pts[q * D + l] = 2.0 * fma(gc->h, gl, p[l]) / gc->pmax - 1.0;
         }
         psamp[q] = gc->h * clenshaw(acc[D], t);
     }
@@ -472,24 +574,31 @@ namespace {
 template <int D, int NUM>
 hipError_t launch_points_n(const cg_general *g)
 {
-    constexpr int G = (16 / D) * D;  // pairs per block
-    const long long pairs = g->hc.NP * D;
-    hipLaunchKernelGGL((k_gen_points<D, NUM>), dim3((unsigned)((pairs + G - 1) / G)), dim3(16 * G), 0, g->stream,
+    // four nodes per block, one wave per player
+    const long long blocks = (g->hc.NP + 3) / 4;
+    hipLaunchKernelGGL((k_gen_points<D, NUM>), dim3((unsigned)blocks), dim3(64 * D), 0, g->stream,
                        g->at<GenConst>(g->L.gc), g->at<GenStatus>(g->L.st), g->at<double>(g->L.U),
                        g->at<double>(g->L.cc), g->at<double>(g->L.pts),
                        g->at<double>(g->L.psamp));
     return hipGetLastError();
 }
 
+int points_num(const GenConst &c)
+{
+    int mx = 0;
+    for (int l = 0; l < c.d; ++l) mx = c.nu[l] > mx ? c.nu[l] : mx;
+    return mx <= 4 ? 4 : mx <= 8 ? 8 : mx <= 12 ? 12 : 16;
+}
+
 template <int D>
 hipError_t launch_points(const cg_general *g)
 {
-    int mx = 0;
-    for (int l = 0; l < D; ++l) mx = g->hc.nu[l] > mx ? g->hc.nu[l] : mx;
-    if (mx <= 4) return launch_points_n<D, 4>(g);
-    if (mx <= 8) return launch_points_n<D, 8>(g);
-    if (mx <= 12) return launch_points_n<D, 12>(g);
-    return launch_points_n<D, 16>(g);
+    switch (points_num(g->hc)) {
+    case 4: return launch_points_n<D, 4>(g);
+    case 8: return launch_points_n<D, 8>(g);
+    case 12: return launch_points_n<D, 12>(g);
+    default: return launch_points_n<D, 16>(g);
+    }
 }
 
 int record(cg_general *g, hipEvent_t *slot)
