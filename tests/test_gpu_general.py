@@ -81,6 +81,22 @@ def test_parity_ragged(cg, orc, d, n_p, n_u, steps, start):
     assert np.max(np.abs(rg - ro) / np.maximum(ro, 1e-300)) < 1e-8
 
 
+@pytest.mark.parametrize("d,n_p,n_u", [
+    (2, (3, 3), (3, 3)),           # the smallest grids
+    (4, (3, 3, 3, 3), (3, 3, 3, 3)),
+    (2, (4, 5), (4, 4)),           # even counts for the last player: two coefficients per lane
+    (3, (5, 4, 3), (12, 7, 10)),   # 12-entry register tiles, five lanes per slice
+    (3, (4, 3, 5), (3, 5, 16)),     # the last player at the 16-node maximum
+])
+def test_small_and_even_sizes(cg, orc, d, n_p, n_u):
+    gg = W.general_game(d, n_p, n_u, seed=50 + d)
+    say(f"  general d={d} n_p={n_p} n_u={n_u}")
+    Vg, Ug, rg, Vo, Uo, ro = _run_pair(cg, orc, gg, 5, start=7)
+    ev, eu = relmax(Vg, Vo), np.max(np.abs(Ug - Uo))
+    say(f"    V rel {ev:.2e}  U abs {eu:.2e}")
+    assert ev < V_TOL and eu < U_TOL
+
+
 def test_largest_sizes(cg, orc):
     # 32 state nodes along one dimension, 16 control nodes for one player
     gg = W.general_game(2, (32, 21), (16, 3), seed=31)
