@@ -243,7 +243,6 @@ __global__ void k_fill_state(double *V, double *U, const GameConst *__restrict__
         U[e] = gc->A[i];
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        st->res_bits[0] = st->res_bits[1] = 0ull;
         st->last_res = 0.0;
         st->converged = 0;
         st->steps_done = 0;
@@ -284,7 +283,6 @@ __global__ void k_arm(GameConst *gc, GameStatus *st, double tol, int clear_done)
         gc->tol = tol;
         st->converged = 0;
         st->nonfinite = 0;
-        st->res_bits[st->cur] = 0ull;
         if (clear_done) st->steps_done = 0;
     }
 }

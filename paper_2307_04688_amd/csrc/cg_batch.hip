@@ -48,7 +48,6 @@ __global__ void k_batch_arm(const Inst *__restrict__ tab, int count, double tol,
     gc->tol = tol;
     st->converged = 0;
     st->nonfinite = 0;
-    st->res_bits[st->cur] = 0ull;
     if (clear_done) st->steps_done = 0;
 }
 
@@ -79,7 +78,6 @@ __global__ void k_batch_reset(const Inst *__restrict__ tab, int count)
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         GameStatus *st = I.st;
-        st->res_bits[0] = st->res_bits[1] = 0ull;
         st->last_res = 0.0;
         st->converged = 0;
         st->steps_done = 0;

@@ -38,7 +38,6 @@ struct GameConst {
 
 // Per-game device status words.
 struct GameStatus {
-    unsigned long long res_bits[2];  // residual of the running step, per state buffer, as bits
     double last_res;                 // residual of the last finished step
     int converged;                   // set once a residual < tol (or non-finite): later steps are no-ops
     int steps_done;                  // iterations performed since the last solve started

@@ -204,12 +204,10 @@ __global__ __launch_bounds__(256) void k_contract_f64(const Inst *__restrict__ t
         }
 }
 
-// End of a step, run by the last block of the line kernel once every block
-// has merged its residual: record the residual, test convergence and
-// finiteness, flip the state buffers, clear the next residual slot.
-__device__ void finish_step(const GameConst *__restrict__ gc, GameStatus *st, int cur)
+// End of a step: record its residual r, test convergence and finiteness,
+// flip the state buffers.
+__device__ void finish_step(const GameConst *__restrict__ gc, GameStatus *st, int cur, double r)
 {
-    const double r = __longlong_as_double(atomicMax(&st->res_bits[cur], 0ull));
     st->steps_done += 1;
     st->total_steps += 1;
     st->last_res = r;
@@ -219,7 +217,6 @@ __device__ void finish_step(const GameConst *__restrict__ gc, GameStatus *st, in
     } else if (gc->tol > 0.0 && r < gc->tol) {
         st->converged = 1;
     }
-    st->res_bits[1 - cur] = 0ull;
     st->cur = 1 - cur;
 }
 
@@ -320,13 +317,14 @@ __global__ __launch_bounds__(COMPOSE ? 64 : 256) void k_line_f64(const Inst *__r
 }
 
 // End of an iteration, one block per instance: the residual is the bitwise
-// maximum of the line kernel's per-block maxima, reduced in a fixed order;
-// then the status bookkeeping.
+// maximum of the line kernel's per-block maxima (non-negative doubles order as
+// their bit patterns, and a NaN's bits exceed every finite value's), then the
+// status bookkeeping.
 __global__ __launch_bounds__(256) void k_finish(const Inst *__restrict__ tab, int nblk)
 {
     const InstView I = inst_view(tab, blockIdx.x);
     GameStatus *st = I.st;
-    __shared__ unsigned long long red[256];
+    __shared__ unsigned long long red[4];
     if (st->converged) return;
     const int tid = threadIdx.x;
     unsigned long long m = 0;
@@ -334,16 +332,18 @@ __global__ __launch_bounds__(256) void k_finish(const Inst *__restrict__ tab, in
         const unsigned long long x = __double_as_longlong(I.blk[k]);
         m = x > m ? x : m;
     }
-    red[tid] = m;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if (tid < w) red[tid] = red[tid + w] > red[tid] ? red[tid + w] : red[tid];
-        __syncthreads();
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const unsigned long long o = __shfl_xor(m, off);
+        m = o > m ? o : m;
     }
+    if ((tid & 63) == 0) red[tid >> 6] = m;
+    __syncthreads();
     if (tid == 0) {
-        const int cur = st->cur;
-        st->res_bits[cur] = red[0];
-        finish_step(I.gc, st, cur);
+        m = red[0];
+#pragma unroll
+        for (int w = 1; w < 4; ++w) m = red[w] > m ? red[w] : m;
+        finish_step(I.gc, st, st->cur, __longlong_as_double(m));
     }
 }
 
