@@ -128,7 +128,7 @@ __device__ __forceinline__ double row16_sum(double v)
 // of the series in u_i; the 16 partial sums of each are combined by
 // row16_sum; one outer index at a time, with at most 128 VGPRs when the
 // (D + 1) NUM accumulators allow it: four waves per SIMD hide more of the
-// load latency than a deeper unroll at three (measured 77.8 against 80.1 us
+// load latency than a deeper unroll at three (measured 74.6 against 80.1 us
 // at d = 3, n_u = 8).  Player D - 1, whose mode has stride 1 in a control tensor:
 // lane s n_u + a keeps coefficient a and every S-th index of mode D - 2
 // (S = 16 / n_u slices; with n_u even, two neighbouring coefficients per lane
