@@ -331,4 +331,112 @@ __device__ __forceinline__ void line_compose(const GameConst *__restrict__ gc, i
     if (NW > 2) q[2] += -0.0625 * h * um * um;
 }
 
+// Value and first derivative of sum_{k<NW} c_k T_k at x (the first two
+// recurrences of clenshaw3).
+template <int NW>
+__device__ __forceinline__ void clenshaw2(const double (&c)[NW], double x, double &f, double &f1)
+{
+    double b1 = 0.0, b2 = 0.0, d1 = 0.0, d2 = 0.0;
+    const double x2 = 2.0 * x;
+#pragma unroll
+    for (int k = NW - 1; k >= 1; --k) {
+        const double b0 = fma(x2, b1, c[k] - b2);
+        const double d0 = fma(x2, d1, 2.0 * b1 - d2);
+        b2 = b1; b1 = b0;
+        d2 = d1; d1 = d0;
+    }
+    f = fma(x, b1, c[0] - b2);
+    f1 = fma(x, d1, b1 - d2);
+}
+
+// First and second derivative at X >= 1 of sum_k |c_k| T_k: every derivative
+// of every T_k is non-negative and non-decreasing on [1, inf), so these bound
+// |sum_k c_k T_k'| and |sum_k c_k T_k''| on [-X, X].
+template <int NW>
+__device__ __forceinline__ void abs_series_bounds(const double (&c)[NW], double X, double &g1, double &g2)
+{
+    double b1 = 0.0, b2 = 0.0, d1 = 0.0, d2 = 0.0, e1 = 0.0, e2 = 0.0;
+    const double x2 = 2.0 * X;
+#pragma unroll
+    for (int k = NW - 1; k >= 1; --k) {
+        const double b0 = fma(x2, b1, fabs(c[k]) - b2);
+        const double d0 = fma(x2, d1, 2.0 * b1 - d2);
+        const double e0 = fma(x2, e1, 4.0 * d1 - e2);
+        b2 = b1; b1 = b0;
+        d2 = d1; d1 = d0;
+        e2 = e1; e1 = e0;
+    }
+    g1 = fma(X, d1, b1 - d2);
+    g2 = fma(X, e1, 2.0 * d1 - e2);
+}
+
+// Step 3 on the line function of line_compose,
+//     v(s) = h G_i(p_i, u(s)) + delta W(a + c s),  W = sum_{k<NW} w_k T_k,
+// without forming its series in s, for the lines that are certainly strictly
+// concave: v''(s) = delta c^2 W''(x) - h u_max^2 / 4 (the payoff is quadratic
+// in u), and with X = max(1, |a| + |c|) the bound of abs_series_bounds on
+// |W''| over the segment certifies v'' <= -h u_max^2 / 8 when
+// delta c^2 sup|W''| <= h u_max^2 / 8.  The maximiser is then found as in the
+// concave branch of line_argmax: an endpoint whose one-sided derivative
+// points outward, or the bracketed Newton iteration on v' from s0, with
+// W, W', W'' at x = a + c s by Clenshaw.  Returns false, touching nothing,
+// when the bound does not certify concavity (the caller composes the series
+// and takes line_argmax).  Exact arithmetic gives the same maximiser as
+// line_argmax on line_compose's coefficients.
+template <int D, int NW>
+__device__ __forceinline__ bool line_argmax_direct(const GameConst *__restrict__ gc, int i, const double (&p)[D],
+                                                   const double (&ub)[D], const double (&b)[D],
+                                                   const double (&w)[NW], double s0, double &v_out,
+                                                   double &s_out)
+{
+    const double h = gc->h, pmax = gc->pmax, um = gc->umax;
+    const double gamma = 2.0 * h * gc->beta[i] / pmax;
+    const double alpha = 2.0 * (p[i] + h * b[i] - h * gc->beta[i] * ub[i]) / pmax - 1.0;
+    const double c = 0.5 * gamma * um;
+    const double a = alpha + c;
+    const double Ai = gc->A[i], dmg = 0.5 * gc->phi[i] * p[i] * p[i], delta = gc->delta;
+    const double curv = 0.25 * h * um * um;  // -d^2/ds^2 of the payoff term
+    double g1, g2;
+    abs_series_bounds(w, fmax(1.0, fabs(a) + fabs(c)), g1, g2);
+    if (!(delta * c * c * g2 <= 0.5 * curv)) return false;  // also catches NaN
+    const double dc = delta * c, dcc = delta * c * c, hu = 0.5 * h * um;
+    // v' at the endpoints: u = 0 at s = -1, u = u_max at s = +1
+    double W, W1;
+    clenshaw2(w, a - c, W, W1);
+    const double fl = fma(dc, W1, hu * Ai);
+    clenshaw2(w, a + c, W, W1);
+    const double fr = fma(dc, W1, hu * (Ai - um));
+    // a few eps of the terms of v' bound its rounding
+    const double floor1 = 1e-15 * (fabs(dc) * g1 + hu * (fabs(Ai) + um));
+    double s;
+    if (fl <= 0.0) {
+        s = -1.0;
+    } else if (fr >= 0.0) {
+        s = 1.0;
+    } else {
+        // the same stopping rules as line_argmax's Newton iteration
+        double lo = -1.0, hi = 1.0;
+        s = fmin(fmax(s0, -1.0), 1.0);
+        for (int it = 0; it < 64; ++it) {
+            double W2;
+            clenshaw3(w, fma(c, s, a), W, W1, W2);
+            const double u = 0.5 * um * (s + 1.0);
+            const double f1 = fma(dc, W1, hu * (Ai - u));
+            const double f2 = fma(dcc, W2, -curv);
+            if (f1 > 0.0) lo = s; else hi = s;
+            if (fabs(f1) <= floor1) break;
+            double sn = s - f1 / f2;
+            const bool newton = sn > lo && sn < hi;
+            if (!newton) sn = 0.5 * (lo + hi);
+            const double step = fabs(sn - s);
+            s = sn;
+            if ((newton && step <= 1e-12) || hi - lo <= 4.5e-16) break;
+        }
+    }
+    const double u = 0.5 * um * (s + 1.0);
+    v_out = fma(delta, clenshaw(w, fma(c, s, a)), h * (u * (Ai - 0.5 * u) - dmg));
+    s_out = s;
+    return true;
+}
+
 }  // namespace cg

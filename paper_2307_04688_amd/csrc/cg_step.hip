@@ -273,8 +273,13 @@ __global__ __launch_bounds__(COMPOSE ? 64 : 256) void k_line_f64(const Inst *__r
     double p[D], ub[D], b[D];
     node_state<D>(gc, Uold, jc, p, ub, b);
     double q[N4];
+    const double s0 = 2.0 * ub[player] / gc->umax - 1.0;  // Newton's start: the current control
+    bool direct = false;
+    double vd = 0.0, sd = 0.0;
     if constexpr (COMPOSE) {
-        line_compose<D, N4>(gc, player, p, ub, b, w, q);
+        // certified concave lines skip the series in s
+        direct = line_argmax_direct<D, N4>(gc, player, p, ub, b, w, s0, vd, sd);
+        if (!direct) line_compose<D, N4>(gc, player, p, ub, b, w, q);
     } else {
         line_fit_regs<D, N4, N4>(gc, player, p, ub, b, w, part, 2, q);
         if (part == 1) {
@@ -289,9 +294,8 @@ __global__ __launch_bounds__(COMPOSE ? 64 : 256) void k_line_f64(const Inst *__r
     }
     double resmax = 0.0;
     if (part == 0 && j < NN) {
-        const double s0 = 2.0 * ub[player] / gc->umax - 1.0;
-        double s;
-        const double vn = line_argmax(q, gc->Nu, s0, s);
+        double s = sd;
+        const double vn = direct ? vd : line_argmax(q, gc->Nu, s0, s);
         const double un = 0.5 * gc->umax * (s + 1.0);
         const long long o = (long long)player * NN + j;
         Vnew[o] = vn;
