@@ -4,7 +4,9 @@
 // Section 3.4) and anisotropic state and control grids.
 //
 // One iteration, for every player i and state node p_j:
-//   transform   coefficients of every V_i^{[r]} (Algorithm Cnv, per mode)
+//   transform   coefficients of every V_i^{[r]} (Algorithm Cnv, per mode:
+//               the two fastest modes of each slice in one launch, the
+//               others in a second that writes the evaluation operand)
 //   points      Step 1: the control polynomials of node j are contracted over
 //               the modes of the other players at their current controls
 //               (the per-node evaluation of Section 3.3), leaving series in
@@ -32,6 +34,7 @@
 
 #include "cg_internal.h"
 #include "cg_line.h"
+#include "cg_tf.h"
 
 namespace {
 
@@ -325,6 +328,114 @@ void k_gen_points(const GenConst *__restrict__ gc, const GenStatus *__restrict__
     }
 }
 
+// Coefficients of every V_i (Algorithm Cnv, Section 3.1: the DCT-I along
+// each mode) on the anisotropic grid, written as the evaluation operand
+// Bp_i[kidx][col] (kidx = (k_0 .. k_{d-3}) N4 + k_{d-2}, col = k_{d-1}; the
+// padding entries stay zero from init), in two launches:
+//   k_gen_tf_inner: one block per (player, position over modes 0 .. d-3): the
+//     slice over the two fastest modes, both passes in LDS; for d = 2 the
+//     slice is the whole tensor and goes straight to the operand, else to
+//     the intermediate coefficient tensor;
+//   k_gen_tf_outer (d >= 3): one block per (player, run of G positions over
+//     the two fastest modes): the plane over modes 0 .. d-3 (one or two
+//     modes), its passes in LDS, then the operand.
+constexpr int kLd = kMaxN + 1;  // LDS row stride (doubles)
+
+template <int D>
+__global__ __launch_bounds__(256) void k_gen_tf_inner(const GenConst *__restrict__ gc,
+                                                      const GenStatus *__restrict__ st,
+                                                      const double *__restrict__ V, double *__restrict__ coef,
+                                                      double *__restrict__ Bp, long long bp_stride, int N4, int NC)
+{
+    __shared__ double X[kMaxN * kLd], Y[kMaxN * kLd];
+    __shared__ double Da[kMaxN * kMaxN], Db[kMaxN * kMaxN];
+    if (st->converged) return;
+    const int tid = threadIdx.x;
+    const int na = gc->np[D - 2], nb = gc->np[D - 1];
+    const int S = na * nb;
+    const long long NP = gc->NP, nsl = NP / S;
+    const int i = (int)(blockIdx.x / nsl);
+    const long long o = blockIdx.x % nsl;
+    const double *src = V + i * NP + o * S;
+    for (int e = tid; e < na * na; e += 256) Da[e] = dct1_entry(e / na, e % na, na);
+    for (int e = tid; e < nb * nb; e += 256) Db[e] = dct1_entry(e / nb, e % nb, nb);
+    for (int e = tid; e < S; e += 256) X[(e / nb) * kLd + e % nb] = src[e];
+    __syncthreads();
+    for (int e = tid; e < S; e += 256) {  // mode D-1
+        const int a = e / nb, l = e % nb;
+        double acc = 0.0;
+        for (int k = 0; k < nb; ++k) acc = fma(Db[l * nb + k], X[a * kLd + k], acc);
+        Y[a * kLd + l] = acc;
+    }
+    __syncthreads();
+    for (int e = tid; e < S; e += 256) {  // mode D-2
+        const int m = e / nb, l = e % nb;
+        double acc = 0.0;
+        for (int k = 0; k < na; ++k) acc = fma(Da[m * na + k], Y[k * kLd + l], acc);
+        if (D == 2)
+            Bp[i * bp_stride + (long long)m * NC + l] = acc;
+        else
+            coef[i * NP + o * S + e] = acc;
+    }
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_gen_tf_outer(const GenConst *__restrict__ gc,
+                                                      const GenStatus *__restrict__ st,
+                                                      const double *__restrict__ coef, double *__restrict__ Bp,
+                                                      long long bp_stride, int N4, int NC, int G)
+{
+    // the plane over modes 0 .. D-3 (n0, or n0 x n1) for G inner positions:
+    // T[(p * G + g)], p the flattened outer index
+    __shared__ double T0[kMaxN * kMaxN], T1[kMaxN * kMaxN];
+    __shared__ double D0[kMaxN * kMaxN], D1[kMaxN * kMaxN];
+    if (st->converged) return;
+    const int tid = threadIdx.x;
+    const int n0 = gc->np[0], n1 = D == 4 ? gc->np[1] : 1;
+    const int na = gc->np[D - 2], nb = gc->np[D - 1];
+    const int S = na * nb, P = n0 * n1;
+    const long long NP = gc->NP;
+    const int runs = (S + G - 1) / G;
+    const int i = blockIdx.x / runs;
+    const int e0 = (blockIdx.x % runs) * G;
+    const int GP = G * P;
+    for (int e = tid; e < n0 * n0; e += 256) D0[e] = dct1_entry(e / n0, e % n0, n0);
+    if (D == 4)
+        for (int e = tid; e < n1 * n1; e += 256) D1[e] = dct1_entry(e / n1, e % n1, n1);
+    const double *src = coef + i * NP;
+    for (int e = tid; e < GP; e += 256) {
+        const int p = e / G, g = e % G;
+        T0[e] = e0 + g < S ? src[(long long)p * S + e0 + g] : 0.0;
+    }
+    __syncthreads();
+    double *cur = T0;
+    if (D == 4) {  // mode 1: p = p0 n1 + p1
+        for (int e = tid; e < GP; e += 256) {
+            const int p = e / G, g = e % G, p0 = p / n1, l = p % n1;
+            double acc = 0.0;
+            for (int k = 0; k < n1; ++k) acc = fma(D1[l * n1 + k], T0[(p0 * n1 + k) * G + g], acc);
+            T1[e] = acc;
+        }
+        __syncthreads();
+        cur = T1;
+    }
+    double *nxt = D == 4 ? T0 : T1;
+    for (int e = tid; e < GP; e += 256) {  // mode 0
+        const int p = e / G, g = e % G, m = p / n1, r = p % n1;
+        double acc = 0.0;
+        for (int k = 0; k < n0; ++k) acc = fma(D0[m * n0 + k], cur[(k * n1 + r) * G + g], acc);
+        nxt[e] = acc;
+    }
+    __syncthreads();
+    for (int e = tid; e < GP; e += 256) {
+        const int p = e / G, g = e % G, pos = e0 + g;
+        if (pos < S) {
+            const int ka = pos / nb, kb = pos % nb;
+            Bp[i * bp_stride + ((long long)p * N4 + ka) * NC + kb] = nxt[e];
+        }
+    }
+}
+
 // Steps 3-4, one thread per (player, node).
 __global__ __launch_bounds__(256) void k_gen_line(const GenConst *__restrict__ gc, const GenStatus *__restrict__ st,
                                                   double *__restrict__ V, double *__restrict__ U,
@@ -601,6 +712,30 @@ hipError_t launch_points(const cg_general *g)
     }
 }
 
+// The transform of every V_i into the evaluation operands (two launches
+// for d >= 3, one for d = 2).
+template <int D>
+hipError_t launch_gen_transform(const cg_general *g)
+{
+    const GenConst &c = g->hc;
+    const int N4 = (c.np[D - 2] + 3) & ~3, NC = c.np[D - 1] <= 16 ? 16 : 32;
+    const int S = c.np[D - 2] * c.np[D - 1];
+    const long long nsl = c.NP / S;
+    double *Bp = g->at<double>(g->L.evws);
+    hipLaunchKernelGGL((k_gen_tf_inner<D>), dim3((unsigned)(D * nsl)), dim3(256), 0, g->stream,
+                       g->at<GenConst>(g->L.gc), g->at<GenStatus>(g->L.st), g->at<double>(g->L.V),
+                       g->at<double>(g->L.coef), Bp, g->bt.bp_stride, N4, NC);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || D == 2) return e;
+    const int P = (int)nsl;               // positions over modes 0 .. D-3 (<= 1024)
+    const int G = P >= 256 ? 1 : 256 / P;  // inner positions per block
+    const int runs = (S + G - 1) / G;
+    hipLaunchKernelGGL((k_gen_tf_outer<D>), dim3((unsigned)(D * runs)), dim3(256), 0, g->stream,
+                       g->at<GenConst>(g->L.gc), g->at<GenStatus>(g->L.st), g->at<double>(g->L.coef), Bp,
+                       g->bt.bp_stride, N4, NC, G);
+    return hipGetLastError();
+}
+
 int record(cg_general *g, hipEvent_t *slot)
 {
     if (!g->prof) return CG_OK;
@@ -627,9 +762,9 @@ int queue_steps(cg_general *g, int nsteps)
         hipEvent_t ev;
         int rc = record(g, &ev);
         if (rc != CG_OK) return rc;
-        GEN_TRY(run_transform(d, n, g->at<double>(g->L.V), g->at<double>(g->L.coef), d, g->stream), "transform");
-        GEN_TRY(pack_eval_f64(d, n, g->at<double>(g->L.coef), d, c.NP, g->at<double>(g->L.evws), g->stream),
-                "pack launch");
+        GEN_TRY(d == 2 ? launch_gen_transform<2>(g) : d == 3 ? launch_gen_transform<3>(g)
+                                                             : launch_gen_transform<4>(g),
+                "transform");
         if ((rc = record(g, &ev)) != CG_OK) return rc;
         hipError_t e = d == 2 ? launch_points<2>(g) : d == 3 ? launch_points<3>(g) : launch_points<4>(g);
         GEN_TRY(e, "points launch");
@@ -734,6 +869,8 @@ int cg_general_init(const cg_general_desc *desc, void *ws_dev, size_t ws_bytes, 
     }
     if (e == hipSuccess)
         e = run_transform(c.d, c.nu, g->at<double>(g->L.cc), g->at<double>(g->L.cc), 2LL * c.d * c.NP, g->stream);
+    // the padding entries of the evaluation operands stay zero from here on
+    if (e == hipSuccess) e = hipMemsetAsync(g->ws + g->L.evws, 0, g->L.evws_bytes, g->stream);
     if (e == hipSuccess) {
         hipLaunchKernelGGL(k_gen_init, dim3(256), dim3(256), 0, g->stream, g->at<GenConst>(g->L.gc),
                            g->at<GenStatus>(g->L.st), g->at<double>(g->L.V), g->at<double>(g->L.U));

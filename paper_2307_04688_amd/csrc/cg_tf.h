@@ -1,12 +1,24 @@
-// cg_tf.h -- device code of the first pass of the game transform (the two
-// fastest modes of every N x N slice) and the packed-operand index, shared
-// by the transform launches and the fused transform + Taylor kernel of the
-// mixed path.
+// cg_tf.h -- device code of the coefficient transform: the DCT-I matrix
+// entries, the first pass of the game transform (the two fastest modes of
+// every N x N slice) and the packed-operand index, shared by the transform
+// launches, the fused transform + Taylor kernel of the mixed path and the
+// general form's transform.
 #pragma once
 
 #include "cg_internal.h"
 
 namespace cg {
+
+// Entry (l, k) of the DCT-I matrix of one mode of size N (n = N - 1):
+// (w_l / n) e_k cos(pi l k / n), w_0 = w_n = 1 else 2, e_0 = e_n = 1/2 else 1.
+__device__ inline double dct1_entry(int l, int k, int N)
+{
+    const int n = N - 1;
+    const int r = (l * k) % (2 * n);
+    double v = cospi((double)r / (double)n);
+    if (k == 0 || k == n) v *= 0.5;
+    return v * ((l == 0 || l == n) ? 1.0 : 2.0) / (double)n;
+}
 
 __device__ __forceinline__ long long packed_index(const GameConst *__restrict__ gc, int i, const int *dig)
 {

@@ -12,15 +12,6 @@
 
 namespace cg {
 
-__device__ inline double dct1_entry(int l, int k, int N)
-{
-    const int n = N - 1;
-    const int r = (l * k) % (2 * n);
-    double v = cospi((double)r / (double)n);
-    if (k == 0 || k == n) v *= 0.5;
-    return v * ((l == 0 || l == n) ? 1.0 : 2.0) / (double)n;
-}
-
 // One pass along a mode: a block owns 256 / N whole fibres, stages them in
 // LDS and writes their N coefficients with one thread per output (so a pass
 // may run in place: every fibre is read before any of it is written, and
