@@ -340,6 +340,14 @@ __global__ __launch_bounds__(256) void k_eval_bf16(const __bf16 *__restrict__ Bp
         const int ch = s / gg.n_o, o = s - ch * gg.n_o;
         if (o == 0) {  // basis products of this chunk, rounded to bf16 once
 #pragma unroll
+            for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const float x = D >= 3 ? xo4[rb][v] : 0.0f;
+                    Fc[rb][v] = x;
+                    Fm[rb][v] = 2.0f * x * x - 1.0f;
+                }
+#pragma unroll
             for (int rb = 0; rb < RB; ++rb) {
                 const int r = wave * 32 + rb * 16 + r16;
 #pragma unroll
@@ -366,29 +374,26 @@ __global__ __launch_bounds__(256) void k_eval_bf16(const __bf16 *__restrict__ Bp
         if (more) load_slab(s + 1);
         f32x4 P[RB][NCB];
 #pragma unroll
-        for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-            for (int c = 0; c < NCB; ++c) P[rb][c] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
         for (int ks = 0; ks < KSC; ++ks) {
 #pragma unroll
             for (int c = 0; c < NCB; ++c) {
                 const bf16x8 b = *reinterpret_cast<const bf16x8 *>(cb + ((ks * NCB + c) * 64 + lane) * 8);
 #pragma unroll
-                for (int rb = 0; rb < RB; ++rb)
-                    P[rb][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[rb][ks], b, P[rb][c], 0, 0, 0);
+                for (int rb = 0; rb < RB; ++rb)  // the first K-step starts from zero
+                    P[rb][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                        a[rb][ks], b, ks == 0 ? f32x4{0.f, 0.f, 0.f, 0.f} : P[rb][c], 0, 0, 0);
             }
         }
-        // outer factor T_o(x_q0) by the three-term recurrence, restarted per chunk
+        // outer factor T_o(x_q0) by the three-term recurrence, one step per
+        // slab with no branch: each chunk restarts it from T_{-1} = T_1 = x
+        // and T_{-2} = T_2 = 2 x^2 - 1, so that its first step gives T_0
+        // (d < 3: x = 0 and every step gives T_0 = 1)
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                float t;
-                if (D < 3 || o == 0) t = 1.0f;
-                else if (o == 1) t = xo4[rb][v];
-                else t = 2.0f * xo4[rb][v] * Fc[rb][v] - Fm[rb][v];
-                Fm[rb][v] = o == 0 ? 0.0f : Fc[rb][v];
+                const float t = 2.0f * xo4[rb][v] * Fc[rb][v] - Fm[rb][v];
+                Fm[rb][v] = Fc[rb][v];
                 Fc[rb][v] = t;
             }
 #pragma unroll
