@@ -547,21 +547,24 @@ static hipError_t launch_eval_bf16_dn(const double *coef, void *ws, const double
 {
     int ksc;
     const Bf16Geo gg = bf16_geo(D, n, ksc);
-    if (n[D - 1] <= 16) {
-        if (D < 4) return launch_bf16_k<D, N4, 16, 1>(coef, ws, x, out, npts, gg, s);
-        switch (ksc) {
-            case 6: return launch_bf16_k<D, N4, 16, 6>(coef, ws, x, out, npts, gg, s);
-            case 4: return launch_bf16_k<D, N4, 16, 4>(coef, ws, x, out, npts, gg, s);
-            case 2: return launch_bf16_k<D, N4, 16, 2>(coef, ws, x, out, npts, gg, s);
-            default: return launch_bf16_k<D, N4, 16, 1>(coef, ws, x, out, npts, gg, s);
+    if constexpr (D < 4) {  // one K-step per chunk (bf16_geo)
+        if (n[D - 1] <= 16) return launch_bf16_k<D, N4, 16, 1>(coef, ws, x, out, npts, gg, s);
+        return launch_bf16_k<D, N4, 32, 1>(coef, ws, x, out, npts, gg, s);
+    } else {
+        if (n[D - 1] <= 16) {
+            switch (ksc) {
+                case 6: return launch_bf16_k<D, N4, 16, 6>(coef, ws, x, out, npts, gg, s);
+                case 4: return launch_bf16_k<D, N4, 16, 4>(coef, ws, x, out, npts, gg, s);
+                case 2: return launch_bf16_k<D, N4, 16, 2>(coef, ws, x, out, npts, gg, s);
+                default: return launch_bf16_k<D, N4, 16, 1>(coef, ws, x, out, npts, gg, s);
+            }
         }
-    }
-    if (D < 4) return launch_bf16_k<D, N4, 32, 1>(coef, ws, x, out, npts, gg, s);
-    switch (ksc) {
-        case 6: return launch_bf16_k<D, N4, 32, 6>(coef, ws, x, out, npts, gg, s);
-        case 4: return launch_bf16_k<D, N4, 32, 4>(coef, ws, x, out, npts, gg, s);
-        case 2: return launch_bf16_k<D, N4, 32, 2>(coef, ws, x, out, npts, gg, s);
-        default: return launch_bf16_k<D, N4, 32, 1>(coef, ws, x, out, npts, gg, s);
+        switch (ksc) {
+            case 6: return launch_bf16_k<D, N4, 32, 6>(coef, ws, x, out, npts, gg, s);
+            case 4: return launch_bf16_k<D, N4, 32, 4>(coef, ws, x, out, npts, gg, s);
+            case 2: return launch_bf16_k<D, N4, 32, 2>(coef, ws, x, out, npts, gg, s);
+            default: return launch_bf16_k<D, N4, 32, 1>(coef, ws, x, out, npts, gg, s);
+        }
     }
 }
 
