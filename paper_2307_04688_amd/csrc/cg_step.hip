@@ -332,7 +332,8 @@ __global__ __launch_bounds__(256) void k_finish(const Inst *__restrict__ tab, in
     if (st->converged) return;
     const int tid = threadIdx.x;
     unsigned long long m = 0;
-    for (int k = tid; k < nblk; k += 256) {
+#pragma unroll 8
+    for (int k = tid; k < nblk; k += 256) {  // eight loads in flight per thread
         const unsigned long long x = __double_as_longlong(I.blk[k]);
         m = x > m ? x : m;
     }
