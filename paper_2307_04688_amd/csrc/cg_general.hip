@@ -34,7 +34,6 @@
 
 #include "cg_internal.h"
 #include "cg_line.h"
-#include "cg_tf.h"
 
 namespace {
 
@@ -53,6 +52,7 @@ struct GenConst {
     double pnode[kMaxD][kMaxN];          // physical state nodes p_max (x_k + 1) / 2
     double tnode[kMaxD][kMaxNu];         // normalised control nodes cos(pi m / (nu - 1))
     double Du[kMaxD][kMaxNu * kMaxNu];   // DCT-I of the fit in u, [l][m], zero-padded
+    double Dp[kMaxD][kMaxN * kMaxN];     // DCT-I of state mode l, [l'][k] (np[l] x np[l])
 };
 
 struct GenStatus {
@@ -357,8 +357,8 @@ __global__ __launch_bounds__(256) void k_gen_tf_inner(const GenConst *__restrict
     const int i = (int)(blockIdx.x / nsl);
     const long long o = blockIdx.x % nsl;
     const double *src = V + i * NP + o * S;
-    for (int e = tid; e < na * na; e += 256) Da[e] = dct1_entry(e / na, e % na, na);
-    for (int e = tid; e < nb * nb; e += 256) Db[e] = dct1_entry(e / nb, e % nb, nb);
+    for (int e = tid; e < na * na; e += 256) Da[e] = gc->Dp[D - 2][e];
+    for (int e = tid; e < nb * nb; e += 256) Db[e] = gc->Dp[D - 1][e];
     for (int e = tid; e < S; e += 256) X[(e / nb) * kLd + e % nb] = src[e];
     __syncthreads();
     for (int e = tid; e < S; e += 256) {  // mode D-1
@@ -399,9 +399,9 @@ __global__ __launch_bounds__(256) void k_gen_tf_outer(const GenConst *__restrict
     const int i = blockIdx.x / runs;
     const int e0 = (blockIdx.x % runs) * G;
     const int GP = G * P;
-    for (int e = tid; e < n0 * n0; e += 256) D0[e] = dct1_entry(e / n0, e % n0, n0);
+    for (int e = tid; e < n0 * n0; e += 256) D0[e] = gc->Dp[0][e];
     if (D == 4)
-        for (int e = tid; e < n1 * n1; e += 256) D1[e] = dct1_entry(e / n1, e % n1, n1);
+        for (int e = tid; e < n1 * n1; e += 256) D1[e] = gc->Dp[1][e];
     const double *src = coef + i * NP;
     for (int e = tid; e < GP; e += 256) {
         const int p = e / G, g = e % G;
@@ -636,6 +636,12 @@ void build_consts(const cg_general_desc *g, GenConst &c)
                 double v = cospi_frac((long long)a * m, nu);
                 if (m == 0 || m == nu) v *= 0.5;
                 c.Du[l][a * kMaxNu + m] = v * ((a == 0 || a == nu) ? 1.0 : 2.0) / (double)nu;
+            }
+        for (int a = 0; a <= n; ++a)
+            for (int k = 0; k <= n; ++k) {
+                double v = cospi_frac((long long)a * k, n);
+                if (k == 0 || k == n) v *= 0.5;
+                c.Dp[l][a * (n + 1) + k] = v * ((a == 0 || a == n) ? 1.0 : 2.0) / (double)n;
             }
     }
 }

@@ -1,8 +1,7 @@
 // cg_tf.h -- device code of the coefficient transform: the DCT-I matrix
 // entries, the first pass of the game transform (the two fastest modes of
 // every N x N slice) and the packed-operand index, shared by the transform
-// launches, the fused transform + Taylor kernel of the mixed path and the
-// general form's transform.
+// launches and the fused transform + Taylor kernel of the mixed path.
 #pragma once
 
 #include "cg_internal.h"
