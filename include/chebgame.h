@@ -141,6 +141,19 @@ int cg_chebyshev_eval(int d, const int32_t *n, const double *coef_dev, const dou
                       int64_t npts, void *out_dev, int precision, void *ws_dev, size_t ws_bytes,
                       void *stream);
 
+/* cg_chebyshev_eval without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, results and errors as
+ * cg_chebyshev_eval (bitwise equal output); the packed coefficient operand
+ * goes to a static device array of the library, 8 MiB + 256 bytes per GPU
+ * (enough for every size in the compiled set; CG_EUNSUPPORTED beyond it),
+ * held until the process ends.  The call allocates nothing.  Every call on a
+ * GPU shares that GPU's array: calls that may overlap on one GPU (other
+ * streams, other threads) race and must be serialised by the caller; calls
+ * queued on one stream are ordered and safe. */
+int cg_chebyshev_eval_noalloc(int d, const int32_t *n, const double *coef_dev, const double *x_dev,
+                              int64_t npts, void *out_dev, int precision, void *stream);
+
 /* nsteps iterations r -> r+1 of Steps 1-4 (Section 2.1, implemented as in
  * Section 3.4): coefficient transform of every V_i^{[r]}, evaluation of V_i at
  * every node's update points p + h g(p, [u_m, u^{[r]}_{-i}(p)]) for the control

@@ -74,6 +74,7 @@ def lib() -> C.CDLL:
     L.cg_eval_workspace_bytes.restype = C.c_size_t
     L.cg_eval_workspace_bytes.argtypes = [C.c_int, ip, C.c_int]
     L.cg_chebyshev_eval.argtypes = [C.c_int, ip, vp, vp, C.c_int64, vp, C.c_int, vp, C.c_size_t, vp]
+    L.cg_chebyshev_eval_noalloc.argtypes = [C.c_int, ip, vp, vp, C.c_int64, vp, C.c_int, vp]
     L.cg_step.argtypes = [vp, C.c_int32, dp]
     L.cg_solve.argtypes = [vp, C.c_int32, C.c_double, ip, dp]
     L.cg_get_state.argtypes = [vp, vp, vp, ip]
@@ -506,6 +507,24 @@ def chebyshev_eval(coef, x, precision: int = FP64, stream=None, out=None):
                                    C.c_void_p(out.data_ptr()), precision, C.c_void_p(ws.data_ptr()), wsb,
                                    C.c_void_p(_stream(stream))))
     out._ws = ws  # keep the workspace alive with the result's lifetime
+    return out
+
+
+def chebyshev_eval_noalloc(coef, x, precision: int = FP64, stream=None, out=None):
+    """chebyshev_eval through cg_chebyshev_eval_noalloc: the library uses its
+    static device scratch and allocates nothing (out, if given, must be a
+    contiguous tensor of npts values of the precision's output type)."""
+    import torch
+    d = coef.dim()
+    n = (C.c_int32 * d)(*coef.shape)
+    coef = coef.to(dtype=torch.float64).contiguous()
+    x = x.to(dtype=torch.float64).contiguous().reshape(-1, d)
+    npts = x.shape[0]
+    odt = torch.float64 if precision == FP64 else torch.float32
+    if out is None:
+        out = torch.empty(npts, dtype=odt, device=coef.device)
+    _check(lib().cg_chebyshev_eval_noalloc(d, n, C.c_void_p(coef.data_ptr()), C.c_void_p(x.data_ptr()), npts,
+                                           C.c_void_p(out.data_ptr()), precision, C.c_void_p(_stream(stream))))
     return out
 
 

@@ -4,6 +4,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -519,26 +520,94 @@ size_t cg_eval_workspace_bytes(int d, const int32_t *n, int precision)
     return eval_ws_bytes(d, nn, precision);
 }
 
-int cg_chebyshev_eval(int d, const int32_t *n, const double *coef_dev, const double *x_dev, int64_t npts,
-                      void *out_dev, int precision, void *ws_dev, size_t ws_bytes, void *stream)
+// Scratch of cg_chebyshev_eval_noalloc: the packed coefficient operand of the
+// evaluation.  Sized for the largest operand of the compiled set (d = 4,
+// N = 32, FP64: 32^3 rows of 32 doubles, plus the 256 bytes of slack every
+// evaluation workspace carries), 8 MiB + 256 B per GPU, held until the
+// process ends.  The packing kernel writes every element the evaluation
+// reads, so nothing has to be cleared between calls.  Host code never uses
+// the array's name as an address: each device's address comes from
+// hipGetSymbolAddress (eval_scratch_ptr).
+constexpr size_t kEvalScratchBytes = (size_t)32 * 32 * 32 * 32 * 8 + 256;
+static __device__ __align__(256) unsigned char scratch[kEvalScratchBytes];
+
+namespace {
+
+// Arguments shared by cg_chebyshev_eval and cg_chebyshev_eval_noalloc; copies
+// the sizes into nn.
+int check_eval_args(int d, const int32_t *n, const double *coef_dev, const double *x_dev, int64_t npts,
+                    const void *out_dev, int precision, int *nn)
 {
     if (d < 1 || d > CG_MAX_D) return fail(CG_EUNSUPPORTED, "d = %d outside [1, %d]", d, CG_MAX_D);
     if (npts < 0) return fail(CG_EINVAL, "npts < 0");
     if (!n || !coef_dev || (npts > 0 && (!x_dev || !out_dev))) return fail(CG_EINVAL, "NULL argument");
     if (precision != CG_FP64 && precision != CG_FP32 && precision != CG_BF16)
         return fail(CG_EUNSUPPORTED, "eval precision %d not supported", precision);
-    int nn[kMaxD];
     for (int l = 0; l < d; ++l) {
         if (n[l] < 2 || n[l] > CG_MAX_N) return fail(CG_EUNSUPPORTED, "n[%d] = %d outside [2, %d]", l, n[l], CG_MAX_N);
         nn[l] = n[l];
     }
+    return CG_OK;
+}
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of 'scratch' on the current device, looked up once per
+// device (with that device current) and kept.
+int eval_scratch_ptr(void **out)
+{
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(CG_EDEVICE, "device %d beyond %d devices", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+        if (!p) return fail(CG_EDEVICE, "hipGetSymbolAddress(scratch) returned NULL");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return CG_OK;
+}
+
+}  // namespace
+
+int cg_chebyshev_eval(int d, const int32_t *n, const double *coef_dev, const double *x_dev, int64_t npts,
+                      void *out_dev, int precision, void *ws_dev, size_t ws_bytes, void *stream)
+{
+    int nn[kMaxD];
+    int rc = check_eval_args(d, n, coef_dev, x_dev, npts, out_dev, precision, nn);
+    if (rc != CG_OK) return rc;
     const size_t need = eval_ws_bytes(d, nn, precision);
     if (need > 0 && (!ws_dev || ws_bytes < need))
         return fail(CG_ENOMEM, "eval workspace has %zu bytes, needs %zu", ws_dev ? ws_bytes : 0, need);
     if (need > 0 && ((uintptr_t)ws_dev & 255) != 0) return fail(CG_EINVAL, "workspace must be 256-byte aligned");
-    int rc = check_device();
+    rc = check_device();
     if (rc != CG_OK) return rc;
     HIP_TRY(launch_eval(d, nn, coef_dev, x_dev, npts, out_dev, precision, ws_dev, ws_bytes, (hipStream_t)stream),
+            "eval launch");
+    return CG_OK;
+}
+
+int cg_chebyshev_eval_noalloc(int d, const int32_t *n, const double *coef_dev, const double *x_dev, int64_t npts,
+                              void *out_dev, int precision, void *stream)
+{
+    int nn[kMaxD];
+    int rc = check_eval_args(d, n, coef_dev, x_dev, npts, out_dev, precision, nn);
+    if (rc != CG_OK) return rc;
+    const size_t need = eval_ws_bytes(d, nn, precision);
+    if (need > kEvalScratchBytes)
+        return fail(CG_EUNSUPPORTED, "eval needs %zu bytes of scratch, the static scratch holds %zu", need,
+                    kEvalScratchBytes);
+    rc = check_device();
+    if (rc != CG_OK) return rc;
+    void *ws = nullptr;
+    rc = eval_scratch_ptr(&ws);
+    if (rc != CG_OK) return rc;
+    HIP_TRY(launch_eval(d, nn, coef_dev, x_dev, npts, out_dev, precision, ws, kEvalScratchBytes,
+                        (hipStream_t)stream),
             "eval launch");
     return CG_OK;
 }
