@@ -112,7 +112,7 @@ def solve_rate(cg, torch, g, prec, time_steps: int, steps: int, warmup: int):
     avg_ms = kernel_ms / max(launches, 1)
     achieved = flops_launch / (avg_ms * 1e-3) / 1e12
     peak = PEAK["fp64"] if prec == cg.FP64 else PEAK["fp32"]
-    kname = "k_contract_f64" if prec == cg.FP64 else "k_contract_corr"
+    kname = "k_contract_f64" if prec == cg.FP64 else ("k_contract_corr3" if g.d == 3 else "k_contract_corr")
     roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
             "traffic": measured_traffic(f"{kname} d={g.d} N={g.N}"), "kernel": kname,
             "avg_launch_ms": avg_ms, "launches": launches, "flops_per_launch": flops_launch}

@@ -119,7 +119,11 @@ Layout layout(const cg_game_desc *g, int precision)
     L.Bp32 = L.E = 0;
     if (precision == CG_FP32_CORR) {
         L.Bp32 = o; o = align256(o + sizeof(float) * (size_t)g->d * K * NC);
-        L.E = o; o = align256(o + sizeof(double) * (size_t)g->d * g->d * (NN / g->n_nodes) * NC);
+        // Taylor tensors [d][d][N^(d-1)][NC] (FP64), then the d = 3 nodal tensors
+        // [d][d-1][N^(d-2)][64 lanes][corr3_chunk] (binary32, fragment order)
+        L.E = o; o = align256(o + sizeof(double) * (size_t)g->d * g->d * (NN / g->n_nodes) * NC +
+                              sizeof(float) * (size_t)g->d * (g->d - 1) * (NN / g->n_nodes / g->n_nodes) * 64 *
+                                  corr3_chunk(N4, NC));
     }
     L.total = o;
     return L;

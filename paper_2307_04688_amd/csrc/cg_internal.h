@@ -36,6 +36,10 @@ struct GameConst {
                                // interpolant of nodal values, [j][k] (normalised x)
 };
 
+// d = 3 mixed contraction: floats per lane of one nodal tensor slab stored
+// in MFMA fragment order (lane-contiguous, padded to whole float4 loads).
+__host__ __device__ constexpr int corr3_chunk(int N4, int NC) { return ((N4 / 4) * (NC / 16) + 3) & ~3; }
+
 // Per-game device status words.
 struct GameStatus {
     double last_res;                 // residual of the last finished step

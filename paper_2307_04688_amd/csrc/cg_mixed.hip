@@ -11,10 +11,13 @@
 // E0 and E1 are small FP64 mode products of V (no point evaluation), computed
 // once per iteration; only the second-order remainder R, of relative size
 // ~Delta^2, runs on binary32 MFMA (inputs rounded to binary32, products
-// accumulated in binary32 over the K-rows of one LDS slab -- N4 or 2 N4 --
+// accumulated in binary32 over a few LDS slabs -- at most 4 N4 K-rows --
 // then added into FP64).
 //
-// A2 is built per K element from per-mode quantities: with T = T_k(x),
+// Two kernels contract R.  d = 3 (k_contract_corr3): the remainder splits
+// into one binary32 product per K element plus two one-mode contractions
+// against nodal tensors (see the kernel).  d = 2, 4 (k_contract_corr): A2 is
+// built per K element from per-mode quantities: with T = T_k(x),
 // Tb = T_k(xbar), P = T_k'(xbar) Delta (first-order increment) and
 // R1 = T - Tb - P, a product over a mode set S extends by a mode c as
 //   Rem_{S+c} = Rem_S T_c + Lin_S R1_c + FO_S P_c,
@@ -102,6 +105,25 @@ __device__ __forceinline__ void taylor_block(const Inst *__restrict__ tab, int b
             for (int t = 0; t < d - 1; ++t) jm = jm * N + (t == s ? r : dig[om[t]]);
             Ei[((long long)(1 + s) * NM + jm) * NC + ki] = acc[v];
             if (s == 0) Ei[(long long)jm * NC + ki] = Gp[r * LD + ki];
+        }
+    }
+    if (d != 3) return;
+    // d = 3: F_l = Dx G, the coefficient tensor with modes l and i transformed
+    // and the third mode (digit f) at its nodes, in binary32 for the
+    // one-mode remainder terms of k_contract_corr3, one N4 x NC slab per
+    // (slot s, digit f) stored in MFMA fragment order: element (r, ki) goes to
+    // lane (r mod 4) 16 + (ki mod 16), entry (r / 4) (NC / 16) + ki / 16 of
+    // that lane's corr3_chunk floats (r < N4, ki < NC; the padding comes out
+    // zero from the zero-padded operands).
+    const int CH = corr3_chunk(gc->N4, NC), NCB = NC / 16;
+    float *E2 = reinterpret_cast<float *>(E + (long long)d * d * NM * NC) + (long long)i * 2 * N * 64 * CH;
+    if (plane_mfma<NP, LD, false, false>(Dx, Gp, wave, lane, acc, ti, tj)) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int r = ti * 16 + kq + 4 * v, ki = tj * 16 + r16;
+            if (r < gc->N4 && ki < NC)
+                E2[(((long long)s * N + f) * 64 + (r & 3) * 16 + (ki & 15)) * CH + (r >> 2) * NCB + (ki >> 4)] =
+                    (float)acc[v];
         }
     }
 }
@@ -451,6 +473,351 @@ __global__ __launch_bounds__(256) void k_contract_corr(const Inst *__restrict__ 
         }
 }
 
+// d = 3 form of the remainder contraction.  With o < n the two modes other
+// than i and, per mode, T = T_k(x), Tb = T_k(xbar), P = T_k'(xbar) Delta,
+// R1 = T - Tb - P and D = T - Tb = P + R1, the Khatri-Rao element splits
+// exactly as
+//   T_o T_n = Tb_o Tb_n + (P_o Tb_n + Tb_o P_n) + (R1_o Tb_n + Tb_o R1_n) + D_o D_n.
+// The first two groups are E0 and the E1 terms (FP64, epilogue).  In the third
+// group one mode sits at its node, so it contracts against the coefficient
+// tensor with that mode at the nodes: sum_o R1_o Co[jn][o] + sum_n R1_n Cn[jo][n]
+// (E2, written by the Taylor launch, one N4 x NC slab per line), 2 N4 K-rows.
+// The last group is the main binary32 GEMM, A = D_o D_n: one product per A
+// element (the outer factor D_o of a row comes from an LDS table), against
+// three for the general recursion above.
+//
+// Rows: the nodes of player i ordered by line, r = (jo N + jn) N + ji, so the
+// 16 rows of an MFMA block share (jo, jn) when N is a multiple of 16; a block
+// that straddles lines runs the E2 terms once per line, the A rows of the
+// other lines masked to zero.  binary32 partial sums enter FP64 every FOLD
+// slabs (FOLD OCB N4 K-rows).
+// Slab sb (OCB outer values) of the packed binary32 coefficients into
+// registers: float4 element e4 = tid + NTHR q of the slab.  Outer values past
+// the last one (slabs padded to whole groups) read the last one's
+// coefficients (their D_o table entries are zero); threads past the slab
+// read a valid element and do not store it.
+template <int PF, int SLAB_E4, int OC_E4, int OCB, int NTHR>
+__device__ __forceinline__ void corr3_load(f32x4 (&pf)[PF], const f32x4 *__restrict__ Bg, int sb, int n_outer,
+                                           int tid)
+{
+#pragma unroll
+    for (int q = 0; q < PF; ++q) {
+        const int e4 = min(tid + q * NTHR, SLAB_E4 - 1);
+        const int oc = min(sb * OCB + e4 / OC_E4, n_outer - 1);
+        pf[q] = Bg[(long long)oc * OC_E4 + e4 % OC_E4];
+    }
+}
+template <int PF, int SLAB_E4, int NC, int LDB, int NTHR>
+__device__ __forceinline__ void corr3_store(const f32x4 (&pf)[PF], float *buf, int tid)
+{
+#pragma unroll
+    for (int q = 0; q < PF; ++q) {
+        const int e4 = tid + q * NTHR;
+        if (e4 < SLAB_E4) {
+            const int e = 4 * e4;
+            *reinterpret_cast<f32x4 *>(buf + (e / NC) * LDB + e % NC) = pf[q];
+        }
+    }
+}
+
+template <int N4, int NC, int RB, int OCB, int FOLD, int WPB, int NX>
+__global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(RB == 1 ? 3 : 1))) void k_contract_corr3(
+    const Inst *__restrict__ tab, int bpi, int blocks_per_player)
+{
+    // NX = N when N is known at compile time (N = N4, every shape of the
+    // benchmark workloads), 0 for the general case.  With NX a multiple of 16
+    // the 16 rows of an MFMA block lie on one line.
+    constexpr int D = 3;
+    constexpr bool ONE_LINE = NX > 0 && NX % 16 == 0;
+    const InstView I = inst_view(tab, blockIdx.x / bpi);
+    const int blk = blockIdx.x % bpi;
+    const GameConst *__restrict__ gc = I.gc;
+    const GameStatus *st = I.st;
+    constexpr int NCB = NC / 16;
+    constexpr int NT = N4 / 4;
+    constexpr int CH = corr3_chunk(N4, NC);      // floats per lane of a nodal slab
+    constexpr int ROWS_W = RB * 16;
+    constexpr int ROWS_B = WPB * ROWS_W;         // WPB waves share every coefficient slab
+    constexpr int NTHR = 64 * WPB;
+    constexpr int LDB = NC == 32 ? 48 : 16;      // slab rows (floats): kq groups on disjoint banks
+    constexpr int SLAB = OCB * N4 * LDB;         // OCB outer values per slab
+    constexpr int OC_E4 = N4 * NC / 4;           // float4 elements per outer value
+    constexpr int SLAB_E4 = OCB * OC_E4;
+    constexpr int PF = (SLAB_E4 + NTHR - 1) / NTHR;
+    constexpr int LDO = N4 + 1;                  // row stride of the D_o table
+    __shared__ float lds[2 * SLAB];
+    __shared__ float dO[ROWS_B * LDO];
+    __shared__ double dls[ROWS_B * 2];           // Delta_o, Delta_n of every row, for the epilogue
+
+    if (st->converged) return;
+    const int cur = st->cur;
+    const int NN = (int)gc->NN;
+    const int N = NX > 0 ? NX : gc->N;
+    const int NM = NN / N;  // nodes of the other modes (lines)
+    const double *Uold = I.U + (long long)cur * D * NN;
+
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int r16 = lane & 15, kq = lane >> 4;
+    const int player = blk / blocks_per_player;
+    const int tile = blk % blocks_per_player;
+    const int row0 = tile * ROWS_B + wave * ROWS_W;
+    const int om0 = player == 0 ? 1 : 0, om1 = player == 2 ? 1 : 2;
+    const int st_i = player == 0 ? N * N : (player == 1 ? N : 1);    // node stride of mode i
+    const int st_o = om0 == 0 ? N * N : N, st_n = om1 == 1 ? N : 1;  // of modes o and n
+    // a / N for 0 <= a < 2^21: exact division when N is a constant, else in
+    // binary32 ((a + 1/2) / N lies at least 1/(2N) from an integer, far beyond
+    // the rounding of the product)
+    const float invN = 1.0f / (float)N;
+    auto divN = [&](int a) { return NX > 0 ? a / NX : (int)(((float)a + 0.5f) * invN); };
+
+    // ---- the first coefficient slab and the nodal tensors of each row block's
+    //      first line (lane-contiguous float4 loads), issued first so that
+    //      their latency overlaps the per-row work ----
+    const f32x4 *Bg = reinterpret_cast<const f32x4 *>(I.Bp32 + (long long)player * gc->K * NC);
+    const int n_outer = N;
+    f32x4 pf0[PF];
+    corr3_load<PF, SLAB_E4, OC_E4, OCB, NTHR>(pf0, Bg, 0, n_outer, tid);
+    const float *E2 = reinterpret_cast<const float *>(I.E + (long long)D * D * NM * NC) +
+                      (long long)player * 2 * N * 64 * CH;
+    f32x4 nbo[RB][CH / 4], nbn[RB][CH / 4];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) {
+        const int L = divN(min(row0 + rb * 16, NN - 1));
+        const int jo = divN(L), jn = L - jo * N;
+        const f32x4 *Bo = reinterpret_cast<const f32x4 *>(E2 + ((long long)jn * 64 + lane) * CH);        // Co[jn]
+        const f32x4 *Bn = reinterpret_cast<const f32x4 *>(E2 + (((long long)N + jo) * 64 + lane) * CH); // Cn[jo]
+#pragma unroll
+        for (int q = 0; q < CH / 4; ++q) {
+            nbo[rb][q] = Bo[q];
+            nbn[rb][q] = Bn[q];
+        }
+    }
+
+    // ---- per row: node, shift, D_n, R1_n, R1_o (this lane's k = 4 t + kq), D_o (table) ----
+    float Dn[RB][NT], R1n[RB][NT], R1o[RB][NT];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) {
+        const int r = min(row0 + rb * 16 + r16, NN - 1);
+        const int L = divN(r), ji = r - L * N;
+        const int jo = divN(L), jn = L - jo * N;
+        const int j = ji * st_i + jo * st_o + jn * st_n;
+        double p[D], ub[D], b[D];
+        node_state<D>(gc, Uold, j, p, ub, b);
+        double xo = 0.0, xn = 0.0;
+#pragma unroll
+        for (int l = 0; l < D; ++l) {
+            const double y = 2.0 * fma(gc->h, b[l], p[l]) / gc->pmax - 1.0;
+            if (l == om0) xo = y;
+            if (l == om1) xn = y;
+        }
+        const double xbo = gc->xnode[jo], xbn = gc->xnode[jn];
+        const int rl = wave * ROWS_W + rb * 16 + r16;
+        if (kq == 0) {
+            dls[rl * 2 + 0] = xo - xbo;
+            dls[rl * 2 + 1] = xn - xbn;
+        }
+        ModeRec4 mo, mn;
+        mo.init(xo, xbo, kq);
+        mn.init(xn, xbn, kq);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            double T, Tb, P, R1;
+            mn.get(T, Tb, P, R1);
+            Dn[rb][t] = (float)(T - Tb);
+            R1n[rb][t] = (float)R1;
+            mn.advance4();
+            mo.get(T, Tb, P, R1);
+            R1o[rb][t] = (float)R1;
+            dO[rl * LDO + 4 * t + kq] = 4 * t + kq < N ? (float)(T - Tb) : 0.f;  // outer values past N: zero rows
+            mo.advance4();
+        }
+    }
+
+    f32x4 acc[RB][NCB];
+    double acc64[RB][NCB][4];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int c = 0; c < NCB; ++c)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc64[rb][c][v] = 0.0;
+
+    // FOLD slabs per group (FOLD OCB = 4 outer values; the last group is
+    // padded with zero rows of A): the first MFMA of a group starts from a
+    // zero accumulator and the group's binary32 sums then enter FP64, with no
+    // branch inside the group; FOLD is even (or OCB FOLD slabs of one) so the
+    // LDS buffer of slab q is fixed.
+    static_assert(OCB * FOLD == 4 && (FOLD % 2 == 0), "four outer values per group, even FOLD");
+    const int n_groups = (n_outer + OCB * FOLD - 1) / (OCB * FOLD);
+    const int n_slabs = n_groups * FOLD;
+    corr3_store<PF, SLAB_E4, NC, LDB, NTHR>(pf0, lds, tid);
+    __syncthreads();  // also publishes the D_o table
+
+    // ---- one-mode remainder terms against the nodal tensors of each line
+    //      (before the main loop: R1_n, R1_o are dead afterwards) ----
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) {
+        const int rbase = row0 + rb * 16;
+        if (rbase >= NN) continue;
+        const int myr = rbase + r16;
+        const int Lfirst = divN(rbase), Llast = ONE_LINE ? Lfirst : divN(min(rbase + 15, NN - 1));
+        for (int L = Lfirst; L <= Llast; ++L) {
+            const bool in = ONE_LINE || (myr < NN && divN(myr) == L);
+            if (L != Lfirst) {  // further lines of a block that straddles lines: their slabs
+                const int jo = divN(L), jn = L - jo * N;
+                const f32x4 *Bo = reinterpret_cast<const f32x4 *>(E2 + ((long long)jn * 64 + lane) * CH);
+                const f32x4 *Bn = reinterpret_cast<const f32x4 *>(E2 + (((long long)N + jo) * 64 + lane) * CH);
+#pragma unroll
+                for (int q = 0; q < CH / 4; ++q) {
+                    nbo[rb][q] = Bo[q];
+                    nbn[rb][q] = Bn[q];
+                }
+            }
+            f32x4 na[NCB];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const float ao = in ? R1o[rb][t] : 0.f, an = in ? R1n[rb][t] : 0.f;
+#pragma unroll
+                for (int c = 0; c < NCB; ++c) {
+                    const int e = t * NCB + c;  // entry of the lane's chunk
+                    const f32x4 cin = t == 0 ? f32x4{0.f, 0.f, 0.f, 0.f} : na[c];
+                    na[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(ao, nbo[rb][e >> 2][e & 3], cin, 0, 0, 0);
+                    na[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(an, nbn[rb][e >> 2][e & 3], na[c], 0, 0, 0);
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < NCB; ++c)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc64[rb][c][v] += (double)na[c][v];
+        }
+    }
+
+    for (int g = 0; g < n_groups; ++g) {
+#pragma unroll
+        for (int q = 0; q < FOLD; ++q) {
+            const int sb = g * FOLD + q;
+            const bool more = sb + 1 < n_slabs;
+            f32x4 pf[PF];
+            // (the last slab loads a valid, unused slab: pf stays unconditionally defined)
+            corr3_load<PF, SLAB_E4, OC_E4, OCB, NTHR>(pf, Bg, more ? sb + 1 : sb, n_outer, tid);
+#pragma unroll
+            for (int ocl = 0; ocl < OCB; ++ocl) {
+                const int oc = sb * OCB + ocl;
+                const float *cb = lds + (q & 1) * SLAB + ocl * N4 * LDB;
+                float bf[NT][NCB];
+#pragma unroll
+                for (int t = 0; t < NT; ++t)
+#pragma unroll
+                    for (int c = 0; c < NCB; ++c) bf[t][c] = cb[(4 * t + kq) * LDB + c * 16 + r16];
+                float fo[RB];
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb) fo[rb] = dO[(wave * ROWS_W + rb * 16 + r16) * LDO + oc];
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+#pragma unroll
+                    for (int rb = 0; rb < RB; ++rb) {
+                        const float a = fo[rb] * Dn[rb][t];
+#pragma unroll
+                        for (int c = 0; c < NCB; ++c) {
+                            const f32x4 cin = (q == 0 && ocl == 0 && t == 0) ? f32x4{0.f, 0.f, 0.f, 0.f}
+                                                                             : acc[rb][c];
+                            acc[rb][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bf[t][c], cin, 0, 0, 0);
+                        }
+                    }
+                }
+            }
+            if (more) corr3_store<PF, SLAB_E4, NC, LDB, NTHR>(pf, lds + ((q + 1) & 1) * SLAB, tid);
+            __syncthreads();
+        }
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int c = 0; c < NCB; ++c)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc64[rb][c][v] += (double)acc[rb][c][v];
+    }
+
+    // ---- epilogue: element v of lane c + 16 kq is row 4 kq + v (f32 layout);
+    //      W = acc64 + E0 + Delta_o E1_o + Delta_n E1_n ----
+    const double *Ei = I.E + (long long)player * D * NM * NC;
+    double *Wp = I.W + (long long)player * NN * NC;
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) {
+        double e0[NCB], e1o[NCB], e1n[NCB];
+        if constexpr (ONE_LINE) {  // one line per block of 16 rows: its E tensors once per column
+            const int L = divN(min(row0 + rb * 16, NN - 1));
+#pragma unroll
+            for (int c = 0; c < NCB; ++c) {
+                const int col = c * 16 + r16;
+                e0[c] = Ei[(long long)L * NC + col];
+                e1o[c] = Ei[((long long)NM + L) * NC + col];
+                e1n[c] = Ei[((long long)2 * NM + L) * NC + col];
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int rl = rb * 16 + 4 * kq + v;
+            const int r = row0 + rl;
+            if (r >= NN) continue;
+            const int L = divN(r), ji = r - L * N;
+            const int jo = divN(L), jn = L - jo * N;
+            const int j = ji * st_i + jo * st_o + jn * st_n;
+            const double dlo = dls[(wave * ROWS_W + rl) * 2 + 0], dln = dls[(wave * ROWS_W + rl) * 2 + 1];
+#pragma unroll
+            for (int c = 0; c < NCB; ++c) {
+                const int col = c * 16 + r16;
+                if constexpr (!ONE_LINE) {
+                    e0[c] = Ei[(long long)L * NC + col];
+                    e1o[c] = Ei[((long long)NM + L) * NC + col];
+                    e1n[c] = Ei[((long long)2 * NM + L) * NC + col];
+                }
+                double w = acc64[rb][c][v] + e0[c];
+                w = fma(dlo, e1o[c], w);
+                w = fma(dln, e1n[c], w);
+                Wp[(long long)j * NC + col] = w;
+            }
+        }
+    }
+}
+
+// Waves per block of the d = 3 mixed contraction (they share every
+// coefficient slab staged in LDS).
+constexpr int kCorr3Waves = 4;
+
+template <int N4, int RB, int NX>
+static hipError_t launch_corr3_nrx(const GameConst &hc, const StepBuffers &b, hipStream_t s)
+{
+    constexpr int NC = N4 <= 16 ? 16 : 32;
+    constexpr int W = kCorr3Waves;
+    const int NN = (int)hc.NN;
+    const int bpp = (NN + W * RB * 16 - 1) / (W * RB * 16);
+    const int bpi = bpp * 3;
+    if (b.ocb == 2)
+        hipLaunchKernelGGL((k_contract_corr3<N4, NC, RB, 2, 2, W, NX>), dim3((unsigned)(bpi * b.count)),
+                           dim3(64 * W), 0, s, b.tab, bpi, bpp);
+    else
+        hipLaunchKernelGGL((k_contract_corr3<N4, NC, RB, 1, 4, W, NX>), dim3((unsigned)(bpi * b.count)),
+                           dim3(64 * W), 0, s, b.tab, bpi, bpp);
+    return hipGetLastError();
+}
+
+template <int N4, int RB>
+static hipError_t launch_corr3_nr(const GameConst &hc, const StepBuffers &b, hipStream_t s)
+{
+    return hc.N == N4 ? launch_corr3_nrx<N4, RB, N4>(hc, b, s) : launch_corr3_nrx<N4, RB, 0>(hc, b, s);
+}
+
+template <int N4>
+static hipError_t launch_corr3_n(const GameConst &hc, const StepBuffers &b, hipStream_t s)
+{
+    switch (b.rb) {
+        case 1: return launch_corr3_nr<N4, 1>(hc, b, s);
+        case 4: return launch_corr3_nr<N4, 4>(hc, b, s);
+        default: return launch_corr3_nr<N4, 2>(hc, b, s);
+    }
+}
+
 template <int D, int N4, int RB>
 static hipError_t launch_corr_dnr(const GameConst &hc, const StepBuffers &b, hipStream_t s)
 {
@@ -495,9 +862,21 @@ static hipError_t launch_corr_d(const GameConst &hc, const StepBuffers &b, hipSt
 
 hipError_t launch_contract_corr(const GameConst &hc, const StepBuffers &b, hipStream_t s)
 {
+    if (hc.d == 3) {
+        switch (hc.N4) {
+            case 4: return launch_corr3_n<4>(hc, b, s);
+            case 8: return launch_corr3_n<8>(hc, b, s);
+            case 12: return launch_corr3_n<12>(hc, b, s);
+            case 16: return launch_corr3_n<16>(hc, b, s);
+            case 20: return launch_corr3_n<20>(hc, b, s);
+            case 24: return launch_corr3_n<24>(hc, b, s);
+            case 28: return launch_corr3_n<28>(hc, b, s);
+            case 32: return launch_corr3_n<32>(hc, b, s);
+        }
+        return hipErrorInvalidValue;
+    }
     switch (hc.d) {
         case 2: return launch_corr_d<2>(hc, b, s);
-        case 3: return launch_corr_d<3>(hc, b, s);
         case 4: return launch_corr_d<4>(hc, b, s);
     }
     return hipErrorInvalidValue;

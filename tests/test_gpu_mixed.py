@@ -73,6 +73,58 @@ def test_mixed_every_step_small_games(cg, orc, d, N, steps):
     say(f"  d={d} N={N}: worst rel V over {steps} steps {worst:.2e}")
 
 
+@pytest.mark.parametrize("d,N", [(3, 32), (3, 24), (3, 20), (3, 13), (4, 24), (4, 21), (2, 32)])
+def test_mixed_one_step_from_smooth_state(cg, orc, d, N):
+    """One mixed step from a seeded smooth state (a value function's shape:
+    quadratic plus sines) against the oracle's step (sampled (player, node)
+    pairs above 5000 nodes): V within 1e-9 of max|V|, u within 1e-8 u_max.  Covers the contraction instantiations of the
+    benchmark shapes (d = 3: N = 32, 24, 20 with lines that straddle the
+    16-row MFMA blocks, ragged 13; d = 4: N = 24 and ragged 21, both N4 = 24)."""
+    say("mixed one step smooth", d, N)
+    g = W.make_game(d, N, seed=60 + d + N, per_player=True)
+    p1 = 0.5 * g.p_max * (np.cos(np.pi * np.arange(N) / (N - 1)) + 1.0)
+    V, U = W.smooth_state(g, p1, seed=60 + N)
+    G = cg.ChebGame(g, cg.FP32_CORR)
+    G.set_state(dev(V), dev(U))
+    G.step(1)
+    Vg, Ug, _ = G.get_state()
+    Vg, Ug = Vg.cpu().numpy(), Ug.cpu().numpy()
+    if N ** d <= 5000:
+        Vo, Uo, _, _ = orc.step(g, V, U)
+    else:
+        idx = np.arange(256 if d < 4 else 128, dtype=np.uint64)
+        pl = (W.uniform(6, 1, idx) * d).astype(int)
+        nd = (W.uniform(6, 2, idx) * N ** d).astype(int)
+        Vs, Us = orc.step_sample(g, V, U, pl, nd)
+        Vo, Uo = np.full_like(V, np.nan), np.full_like(U, np.nan)
+        Vo[pl, nd], Uo[pl, nd] = Vs, Us
+    m = ~np.isnan(Vo)
+    ev = np.max(np.abs(Vg[m] - Vo[m])) / np.max(np.abs(Vo[m]))
+    eu = np.max(np.abs(Ug[m] - Uo[m])) / g.u_max
+    say(f"  rel V {ev:.2e}  u {eu:.2e}")
+    assert ev <= 1e-9 and eu <= 1e-8
+
+
+@pytest.mark.parametrize("d,N,steps", [(4, 24, 5), (4, 21, 5), (3, 32, 8), (3, 24, 8)])
+def test_mixed_steps_from_zero_against_lq_recursion(cg, d, N, steps):
+    """Several mixed steps from the zero terminal value against the exact
+    linear-quadratic recursion (while no control is at its bound every
+    iterate is a quadratic that the Chebyshev iteration reproduces), at every
+    node: V within 1e-9 of max|V|, u within 1e-8 u_max."""
+    from lq_recursion import lq_nodal
+    say("mixed steps from zero vs LQ", d, N, steps)
+    g = W.make_game(d, N, seed=70 + d + N, per_player=True)
+    G = cg.ChebGame(g, cg.FP32_CORR)
+    G.step(steps)
+    Vg, Ug, _ = G.get_state()
+    Vl, Ul = lq_nodal(g, steps)
+    assert np.min(Ul) > 0
+    ev = np.max(np.abs(Vg.cpu().numpy() - Vl)) / np.max(np.abs(Vl))
+    eu = np.max(np.abs(Ug.cpu().numpy() - Ul)) / g.u_max
+    say(f"  rel V {ev:.2e}  u {eu:.2e}")
+    assert ev <= 1e-9 and eu <= 1e-8
+
+
 def _basis(n, x):
     """T_0..T_{n-1}(x) and T_k'(x) for scalar x (numpy chebyshev)."""
     V = npc.chebvander(np.array([x]), n - 1)[0]
@@ -85,17 +137,20 @@ def test_one_step_within_a_priori_bound(cg, orc):
     steps) against the oracle's step, per sampled (player, node), within
 
         |dV| <= delta * sum_{k_i} max_line |T_{k_i}| * |dw_{k_i}|,
-        |dw_{k_i}| <= (8 u + gamma_{2 N4}(u)) * sum_K S_K |c[K, k_i]|   (u = 2^-24),
-        S = |R1_a T_c| + |(Tb_a + P_a) R1_c| + |P_a P_c|,
+        |dw_{k_i}| <= (4 u + gamma_{4 N4}(u)) * sum_K S_K |c[K, k_i]|   (u = 2^-24),
+        S = |D_a D_c| + |Tb_a R1_c| + |R1_a Tb_c|,
 
-    where A2 = R1_a T_c + (Tb_a + P_a) R1_c + P_a P_c is the second-order
-    remainder of the Khatri-Rao basis at the shifted point, the only part
-    contracted in binary32: six binary32 factors and c each rounded once, three
-    rounded operations to form an element (the terms may cancel, hence S),
-    products accumulated in binary32 over the K-rows of one coefficient slab
-    (up to 2 N4) and then in FP64.  A2 and
-    the coefficients come from numpy and the oracle.  The FP64 rest of the
-    step adds its own budget, 1e-13 max|V|."""
+    for d = 3 with a < c the modes other than i, D = T - Tb and R1 = T - Tb
+    - T'(xbar) Delta per mode.  The binary32 part of the contraction is the
+    second-order remainder KR(x) - KR(xbar) - sum_l Delta_l dKR/dx_l(xbar) =
+    D_a D_c + Tb_a R1_c + R1_a Tb_c: the first term with A = D_a D_c (two
+    rounded factors, one rounded product), the other two as one-mode
+    contractions against the coefficient tensor with the other mode at its
+    node (computed in FP64, rounded once), every coefficient rounded once,
+    products summed in binary32 over at most four outer values (4 N4 K-rows)
+    and then in FP64.  The terms are bounded by magnitude (hence S).  A_2
+    and the coefficients come from numpy and the oracle.  The FP64 rest of
+    the step adds its own budget, 1e-13 max|V|."""
     g = W.make_game(3, 12, seed=9, per_player=True)
     V, U, _ = orc.solve(g, 12)
     Vo, Uo, _, _ = orc.step(g, V, U)
@@ -110,8 +165,8 @@ def test_one_step_within_a_priori_bound(cg, orc):
     delta = 1 - g.rho * g.h
     u32 = 2.0 ** -24
     N4 = (N + 3) // 4 * 4
-    KS = 2 * N4                       # K-rows summed in binary32 per slab
-    factor = 8 * u32 + KS * u32 / (1 - KS * u32)
+    KS = 4 * N4                       # K-rows summed in binary32 before FP64
+    factor = 4 * u32 + KS * u32 / (1 - KS * u32)
     idx = np.arange(48, dtype=np.uint64)
     players = (W.uniform(9, 3, idx) * d).astype(int)
     nodes = (W.uniform(9, 4, idx) * N ** d).astype(int)
@@ -131,8 +186,9 @@ def test_one_step_within_a_priori_bound(cg, orc):
             P[l] = Dl * (x[l] - xb[l])
             R1[l] = T[l] - Tb[l] - P[l]
         a, c = others
-        S = (np.abs(np.outer(R1[a], T[c])) + np.abs(np.outer(Tb[a] + P[a], R1[c]))
-             + np.abs(np.outer(P[a], P[c])))
+        D = {l: T[l] - Tb[l] for l in others}
+        S = (np.abs(np.outer(D[a], D[c])) + np.abs(np.outer(Tb[a], R1[c]))
+             + np.abs(np.outer(R1[a], Tb[c])))
         cm = np.moveaxis(coef, i, -1)                     # [k_a, k_c, k_i]
         dw = factor * np.einsum("ac,aci->i", S, np.abs(cm))
         # line points: x_i over the control range

@@ -159,6 +159,22 @@ def random_state(game: Game, seed: int, stream: int = 77, scale: float = 1.0):
     return V.reshape(game.d, game.n_nodes), U.reshape(game.d, game.n_nodes)
 
 
+def smooth_state(game: Game, pnodes, seed: int, stream: int = 92):
+    """Seeded smooth state (V, U), each (d, N**d), C order over nodes, at the
+    given 1-D node coordinates (physical, the same along every dimension):
+    V_i(p) = -sum_l a_il (p_l/P_M)^2 + 0.2 sum_l sin(w_il p_l/P_M + s_il),
+    u_i(p) = U_M (0.5 + 0.3 sin(sum_l v_il p_l / P_M)) -- the shape of a value
+    function after some iterations (entire functions, so their Chebyshev
+    coefficients decay faster than geometrically)."""
+    d = game.d
+    r = uniform(seed, stream, np.arange(5 * d * d, dtype=np.uint64)).reshape(5, d, d)
+    P = np.stack(np.meshgrid(*([np.asarray(pnodes, dtype=np.float64)] * d), indexing="ij"),
+                 axis=-1).reshape(-1, d) / game.p_max
+    V = -(P * P) @ (0.5 + r[0]).T + 0.2 * np.sin(P[:, None, :] * (1.0 + 2.0 * r[1])[None] + 6.0 * r[2][None]).sum(-1)
+    U = game.u_max * (0.5 + 0.3 * np.sin(P @ (2.0 * r[3] - 1.0).T * 3.0))
+    return np.ascontiguousarray(V.T), np.ascontiguousarray(U.T)
+
+
 def coef_tensor(d: int, N: int, seed: int, decay: float = 0.3) -> np.ndarray:
     """c_k = N(0,1) * exp(-decay * sum(k)), shape (N,)*d, FP64 (stream 0)."""
     g = normal(seed, 0, N ** d).reshape((N,) * d)
