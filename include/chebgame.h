@@ -186,8 +186,10 @@ int cg_set_state(cg_game *game, const double *V_dev, const double *U_dev);
  * advanced together.  Games with the same d, N, precision and control-fit
  * path form a group; one iteration of every group is a fixed sequence of
  * kernel launches, each covering all games of its group (blocks are mapped
- * to (game, player, node tile) through a device table).  That sequence is
- * captured once in a hipGraph and replayed per iteration.  Each game keeps
+ * to (game, player, node tile) through a device table).  One iteration of
+ * all groups is captured once in a hipGraph, the groups spread over up to
+ * four parallel branches (balanced by their contraction work) so that small
+ * groups run beside large ones, and replayed per iteration.  Each game keeps
  * its own state, status and convergence test (Step 4): a converged game's
  * blocks return at once.
  *

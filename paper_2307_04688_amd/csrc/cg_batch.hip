@@ -1,6 +1,7 @@
 // cg_batch.hip -- batched value iteration over many games (C ABI part of
 // include/chebgame.h): grouping, device tables, one captured iteration
-// replayed as a hipGraph, and the row-blocking autotuner.
+// (groups spread over parallel graph branches) replayed as a hipGraph, and
+// the tile autotuner.
 #include <stdio.h>
 #include <string.h>
 
@@ -13,6 +14,12 @@
 using namespace cg;
 
 namespace {
+
+// Parallel branches of the captured iteration: groups are spread over up to
+// this many capture streams that fork from and join into one stream, so the
+// replayed graph runs independent groups concurrently (the runtime maps graph
+// branches to its hardware queues).
+constexpr int kBranches = 4;
 
 struct Group {
     GameConst hc;              // constants of the first game (d, N, sizes)
@@ -95,10 +102,14 @@ struct cg_batch {
     size_t all_tab_off;        // table of every game (for arm / gather / reset)
     size_t status_off;         // StatusCopy[count]
     hipStream_t stream;        // caller's stream
-    hipStream_t cap;           // private stream used for capture only
+    hipStream_t cap;           // private stream used for capture only (branch 0)
+    hipStream_t side[kBranches - 1];   // capture streams of the other branches
+    hipEvent_t fork, join[kBranches - 1];
     hipGraph_t graph;
     hipGraphExec_t exec;
     bool have_graph;
+    int branches;              // parallel branches of the captured iteration
+    std::vector<int> branch_of;  // per group
     std::vector<StatusCopy> host_status;
     ~cg_batch()
     {
@@ -107,6 +118,11 @@ struct cg_batch {
             (void)hipGraphDestroy(graph);
         }
         if (cap) (void)hipStreamDestroy(cap);
+        for (int b = 0; b < kBranches - 1; ++b) {
+            if (side[b]) (void)hipStreamDestroy(side[b]);
+            if (join[b]) (void)hipEventDestroy(join[b]);
+        }
+        if (fork) (void)hipEventDestroy(fork);
     }
 };
 
@@ -124,7 +140,7 @@ StepBuffers group_buffers(cg_batch *B, const Group &G)
     return b;
 }
 
-// Queue one iteration of every group on stream s.
+// Queue one iteration of every group on stream s (autotuning, one branch).
 hipError_t queue_iteration(cg_batch *B, hipStream_t s)
 {
     for (const Group &G : B->groups) {
@@ -134,6 +150,50 @@ hipError_t queue_iteration(cg_batch *B, hipStream_t s)
     return hipSuccess;
 }
 
+// Relative cost of one iteration of a group: its contraction flops, with a
+// floor for the latency of its launches.
+double group_cost(const Group &G)
+{
+    const double flops = (double)G.members.size() * G.hc.d * 2.0 * (double)G.hc.NN * (double)G.hc.NN / G.hc.N;
+    return flops + 2e8;
+}
+
+// Groups to branches: largest first, each to the currently cheapest branch.
+void assign_branches(cg_batch *B)
+{
+    const int ng = (int)B->groups.size();
+    B->branches = std::min(kBranches, ng);
+    B->branch_of.assign(ng, 0);
+    std::vector<double> load(B->branches, 0.0);
+    for (int g = 0; g < ng; ++g) {  // groups are sorted largest first
+        int best = 0;
+        for (int b = 1; b < B->branches; ++b)
+            if (load[b] < load[best]) best = b;
+        B->branch_of[g] = best;
+        load[best] += group_cost(B->groups[g]);
+    }
+}
+
+// One iteration captured with branch b's groups on its own stream, forked
+// from and joined into the capture stream.
+hipError_t capture_iteration(cg_batch *B)
+{
+    hipError_t e = hipSuccess;
+    if (B->branches > 1) {
+        e = hipEventRecord(B->fork, B->cap);
+        for (int b = 1; b < B->branches && e == hipSuccess; ++b) e = hipStreamWaitEvent(B->side[b - 1], B->fork, 0);
+    }
+    for (size_t g = 0; g < B->groups.size() && e == hipSuccess; ++g) {
+        const int b = B->branch_of[g];
+        e = launch_step(B->groups[g].hc, group_buffers(B, B->groups[g]), b == 0 ? B->cap : B->side[b - 1]);
+    }
+    for (int b = 1; b < B->branches && e == hipSuccess; ++b) {
+        e = hipEventRecord(B->join[b - 1], B->side[b - 1]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(B->cap, B->join[b - 1], 0);
+    }
+    return e;
+}
+
 int build_graph(cg_batch *B)
 {
     if (B->have_graph) {
@@ -141,9 +201,10 @@ int build_graph(cg_batch *B)
         (void)hipGraphDestroy(B->graph);
         B->have_graph = false;
     }
+    assign_branches(B);
     hipError_t e = hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_err(e, "hipStreamBeginCapture");
-    hipError_t eq = queue_iteration(B, B->cap);
+    hipError_t eq = capture_iteration(B);
     e = hipStreamEndCapture(B->cap, &B->graph);
     if (eq != hipSuccess) return hip_err(eq, "capture of one iteration");
     if (e != hipSuccess) return hip_err(e, "hipStreamEndCapture");
@@ -200,7 +261,13 @@ int cg_batch_create(cg_game *const *games, int32_t count, void *ws_dev, size_t w
     B->ws = (char *)ws_dev;
     B->stream = (hipStream_t)stream;
     B->cap = nullptr;
+    B->fork = nullptr;
+    for (int b = 0; b < kBranches - 1; ++b) {
+        B->side[b] = nullptr;
+        B->join[b] = nullptr;
+    }
     B->have_graph = false;
+    B->branches = 1;
     B->host_status.resize(count);
     // group by (d, N, control-fit path, precision)
     for (int i = 0; i < count; ++i) {
@@ -255,7 +322,13 @@ int cg_batch_create(cg_game *const *games, int32_t count, void *ws_dev, size_t w
         if (e != hipSuccess) break;
     }
     if (e == hipSuccess) e = hipStreamSynchronize(B->stream);  // host tables go out of scope
+    // capture streams (default priority) and the fork / join events
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking);
+    for (int b = 0; b < kBranches - 1 && e == hipSuccess; ++b) {
+        e = hipStreamCreateWithFlags(&B->side[b], hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&B->join[b], hipEventDisableTiming);
+    }
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&B->fork, hipEventDisableTiming);
     if (e != hipSuccess) {
         delete B;
         return hip_err(e, "cg_batch_create");

@@ -3,8 +3,8 @@ linear-quadratic game: first-order convergence in h, as the oracle shows."""
 import numpy as np
 import pytest
 
-import riccati
 import workloads as W
+from workloads import continuous as riccati
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -25,12 +25,16 @@ def nodes_phys(orc, g):
 
 
 def test_first_order_in_h_on_gpu(cg, orc):
+    """Policy error against the continuous-time equilibrium for h from 0.1 down
+    to 1e-3: halving h halves it, and over the two decades the log-log slope
+    is one."""
     print("accuracy study on the GPU", flush=True)
     errs, ustar = [], None
-    for h in (0.1, 0.05, 0.025, 0.0125):
+    hs = (0.1, 0.05, 0.025, 0.0125, 0.002, 0.001)
+    for h in hs:
         g = W.make_game(2, 5, seed=1, nominal=True, h=h, p_max=0.5)
         G = cg.ChebGame(g, cg.FP64)
-        rc, n, r = G.solve(100000, 1e-12)
+        rc, n, r = G.solve(1000000, 1e-12)
         assert rc == cg.OK
         V, U, _ = G.get_state()
         V, U = V.cpu().numpy(), U.cpu().numpy()
@@ -42,6 +46,8 @@ def test_first_order_in_h_on_gpu(cg, orc):
             Vo, Uo, _ = orc.solve(g, 100000, tol=1e-12)
             assert np.max(np.abs(U - Uo)) < 1e-9           # GPU and oracle reach the same fixed point
         errs.append(np.max(np.abs(U - ustar)))
-    rates = [errs[k] / errs[k + 1] for k in range(len(errs) - 1)]
-    print("  max policy error", errs, "ratios", rates, flush=True)
+    rates = [errs[k] / errs[k + 1] for k in (0, 1, 2, 4)]          # h halved
+    slope = np.polyfit(np.log(hs), np.log(errs), 1)[0]
+    print("  max policy error", errs, "ratios", rates, "slope", slope, flush=True)
     assert all(1.7 < q < 2.3 for q in rates)
+    assert 0.95 < slope < 1.05

@@ -67,6 +67,55 @@ def test_batch_against_oracle(cg, orc):
         assert np.max(np.abs(U.cpu().numpy() - Uo)) <= 1e-10 * g.u_max
 
 
+def c4_shape_games():
+    """The first instances of the 256-game ragged workload (seed 4) with the
+    large shapes: d = 3 at N = 32 and 24, d = 2 at N = 32."""
+    want, out = [(3, 32), (2, 32), (3, 24)], []
+    for g in W.batch_games(256):
+        if (g.d, g.N) in want and not any((o.d, o.N) == (g.d, g.N) for o in out):
+            out.append(g)
+    return out
+
+
+def test_batch_c4_shapes_mixed_against_lq_and_oracle(cg, orc):
+    """Mixed batch of the workload's large shapes: 20 iterations from zero
+    against the exact linear-quadratic recursion at every node (no control
+    reaches its bound within 20 iterations), then one more iteration against
+    the oracle's step from the batch's own state at 128 sampled (player,
+    node) pairs per game.  V within 1e-9 of max|V|, u within 1e-8 u_max."""
+    from lq_recursion import lq_nodal
+    games = c4_shape_games()
+    say(f"batch C4 shapes: {[(g.d, g.N) for g in games]}")
+    handles = [cg.ChebGame(g, cg.FP32_CORR) for g in games]
+    B = cg.ChebBatch(handles)
+    rc, steps, _ = B.solve(20)
+    assert rc == cg.OK and np.all(steps == 20)
+    states = []
+    for g, h in zip(games, handles):
+        V, U, _ = h.get_state()
+        V, U = V.cpu().numpy(), U.cpu().numpy()
+        Vl, Ul = lq_nodal(g, 20)
+        assert np.min(Ul) > 0
+        ev = np.max(np.abs(V - Vl)) / np.max(np.abs(Vl))
+        eu = np.max(np.abs(U - Ul)) / g.u_max
+        say(f"  d={g.d} N={g.N}: 20 iterations vs LQ: rel V {ev:.2e} u {eu:.2e}")
+        assert ev <= 1e-9 and eu <= 1e-8
+        states.append((V, U))
+    B.solve(1)
+    for k, (g, h) in enumerate(zip(games, handles)):
+        V, U = states[k]
+        idx = np.arange(128, dtype=np.uint64)
+        pl = (W.uniform(20 + k, 1, idx) * g.d).astype(int)
+        nd = (W.uniform(20 + k, 2, idx) * g.N ** g.d).astype(int)
+        Vs, Us = orc.step_sample(g, V, U, pl, nd)
+        V1, U1, _ = h.get_state()
+        V1, U1 = V1.cpu().numpy()[pl, nd], U1.cpu().numpy()[pl, nd]
+        ev = np.max(np.abs(V1 - Vs)) / np.max(np.abs(Vs))
+        eu = np.max(np.abs(U1 - Us)) / g.u_max
+        say(f"  d={g.d} N={g.N}: iteration 21 vs oracle: rel V {ev:.2e} u {eu:.2e}")
+        assert ev <= 1e-9 and eu <= 1e-8
+
+
 def test_batch_convergence_per_instance(cg):
     """Each game stops at its own first residual below tol, exactly where its
     own solve stops; with a long step (h = 0.2) one of these games keeps

@@ -4,8 +4,8 @@ policy error shrinks at first order in h (the Euler step of the scheme)."""
 import numpy as np
 
 import oracle
-import riccati
 import workloads as W
+from workloads import continuous as riccati
 
 
 def nodes_phys(g):

@@ -1,5 +1,7 @@
 """Continuous-time feedback Nash equilibrium of the linear-quadratic pollution
-game (Section 2 with the examples' quadratic benefit and damage), for tests.
+game (Section 2 with the examples' quadratic benefit and damage): the
+yardstick of the accuracy study of Section 4.1 (the tests and the benchmark's
+accuracy workload compare the iteration's policy with it).
 
 With V_i(p) = alpha_i + b_i . p + p' C_i p / 2 the first-order condition of the
 HJB equation  rho V_i = max_{u_i} [u_i (A_i - u_i/2) - phi_i p_i^2/2 + grad V_i . g(p, u)],
@@ -8,7 +10,7 @@ positive); the HJB residual is then a quadratic polynomial in p, and its
 coefficients vanish at the solution.  They are matched here by least squares
 on sample points, started from a quadratic fit of a numerical solution, so the
 equilibrium found is the one the iteration converges to.
-Independent of the oracle and of the GPU library.
+Independent of the oracle and of the GPU library; not part of the method.
 """
 import numpy as np
 from scipy.optimize import least_squares
