@@ -9,18 +9,31 @@
  * code, header, table or helper with it.
  *
  * Every function computes its result from the plain definition in the
- * paper, in IEEE binary64, built with -O2 -ffp-contract=off (no fused
- * multiply-add, no fast-math).  Readings of places where the paper is silent
- * or garbled are marked "Reading:".
+ * paper, in IEEE binary64 (see OR_REAL below), built with -O2
+ * -ffp-contract=off (no fused multiply-add, no fast-math).  Readings of
+ * places where the paper is silent or garbled are marked "Reading:".
  *
  * Array conventions: an n-dimensional array of shape N[0] x ... x N[d-1] is
  * stored in C order (last mode fastest).  Index k of a mode is the Lobatto
  * node x_k = cos(pi k / (N-1)), so index 0 is x = +1.
  */
-#include <math.h>
+#include <tgmath.h>
 #include <omp.h>
 #include <stdlib.h>
 #include <string.h>
+
+/* Arithmetic type.  The oracle is binary64 (OR_REAL undefined: double).
+ * The same source built with -DOR_REAL="long double" (x87 extended format,
+ * 64-bit significand, unit roundoff 2^-64 against 2^-53) is a second
+ * reference whose rounding error is 2^-11 of the binary64 one: it measures
+ * the binary64 oracle's own rounding error, nothing else changes.  Every
+ * array and scalar below is of this type; <tgmath.h> picks cos/fabs/fmax of
+ * the same precision. */
+#ifndef OR_REAL
+#define OR_REAL double
+#endif
+typedef OR_REAL real;
+#define OR_PI ((real)3.14159265358979323846264338327950288L)
 
 #define OR_MAXD 4
 #define OR_MAXN 64
@@ -31,16 +44,16 @@ int or_num_threads(void) { return omp_get_max_threads(); }
 /* cos(pi a / n) with a reduced modulo 2n first, so the argument stays in
  * [0, 2 pi).  Chebyshev nodes and T_l(alpha^k) = cos(pi l k / n) (Section
  * 3.1) both use it. */
-static double cos_pi_frac(long a, long n)
+static real cos_pi_frac(long a, long n)
 {
     long r = a % (2 * n);
     if (r < 0) r += 2 * n;
-    return cos(M_PI * (double)r / (double)n);
+    return cos(OR_PI * (real)r / (real)n);
 }
 
 /* Chebyshev-Lobatto nodes alpha^k = cos(pi k / n), k = 0..n, n = N-1 (Section
  * 3.1, the extrema of T_n). */
-void or_nodes(int N, double *x)
+void or_nodes(int N, real *x)
 {
     int n = N - 1;
     for (int k = 0; k < N; ++k) x[k] = (n == 0) ? 1.0 : cos_pi_frac(k, n);
@@ -50,7 +63,7 @@ void or_nodes(int N, double *x)
  * Equals cos(k arccos x) on [-1,1] (Section 3.1) and continues the same
  * polynomials outside it.  Reading: update points that leave the box by
  * O(h) are evaluated by polynomial extrapolation, not clamped. */
-void or_cheb_T(int cnt, double x, double *T)
+void or_cheb_T(int cnt, real x, real *T)
 {
     if (cnt > 0) T[0] = 1.0;
     if (cnt > 1) T[1] = x;
@@ -62,19 +75,19 @@ void or_cheb_T(int cnt, double x, double *T)
  *   p_l = (w_l / n) sum''_{k=0..n} F_k T_l(alpha^k),  w_l = 1 for l in {0,n},
  *   else 2; the double prime halves the k = 0 and k = n terms.
  * Input F and output p are strided views of length N = n+1. */
-void or_coef_1d(int N, const double *F, long fstride, double *p, long pstride)
+void or_coef_1d(int N, const real *F, long fstride, real *p, long pstride)
 {
     int n = N - 1;
     if (n == 0) { p[0] = F[0]; return; }
     for (int l = 0; l <= n; ++l) {
-        double s = 0.0;
+        real s = 0.0;
         for (int k = 0; k <= n; ++k) {
-            double term = F[k * fstride] * cos_pi_frac((long)l * k, n);
+            real term = F[k * fstride] * cos_pi_frac((long)l * k, n);
             if (k == 0 || k == n) term *= 0.5;
             s += term;
         }
-        double w = (l == 0 || l == n) ? 1.0 : 2.0;
-        p[l * pstride] = (w / (double)n) * s;
+        real w = (l == 0 || l == n) ? 1.0 : 2.0;
+        p[l * pstride] = (w / (real)n) * s;
     }
 }
 
@@ -82,22 +95,22 @@ void or_coef_1d(int N, const double *F, long fstride, double *p, long pstride)
  * eq. (forcoef) along every mode in turn.  'order' lists the modes in the
  * order they are processed (NULL = 0..d-1); the result does not depend on it
  * because the n-dimensional transform is a tensor product of 1-D ones. */
-void or_transform(int d, const int *N, const int *order, const double *vals, double *coef)
+void or_transform(int d, const int *N, const int *order, const real *vals, real *coef)
 {
     long total = 1;
     for (int l = 0; l < d; ++l) total *= N[l];
-    double *buf = (double *)malloc(sizeof(double) * (size_t)total);
-    double *tmp = (double *)malloc(sizeof(double) * OR_MAXN);
-    memcpy(coef, vals, sizeof(double) * (size_t)total);
+    real *buf = (real *)malloc(sizeof(real) * (size_t)total);
+    real *tmp = (real *)malloc(sizeof(real) * OR_MAXN);
+    memcpy(coef, vals, sizeof(real) * (size_t)total);
     for (int t = 0; t < d; ++t) {
         int m = order ? order[t] : t;
         long stride = 1;
         for (int l = m + 1; l < d; ++l) stride *= N[l];
         long outer = total / (stride * N[m]);
-        memcpy(buf, coef, sizeof(double) * (size_t)total);
+        memcpy(buf, coef, sizeof(real) * (size_t)total);
         for (long o = 0; o < outer; ++o)
             for (long in = 0; in < stride; ++in) {
-                const double *F = buf + o * N[m] * stride + in;
+                const real *F = buf + o * N[m] * stride + in;
                 or_coef_1d(N[m], F, stride, tmp, 1);
                 for (int l = 0; l < N[m]; ++l) coef[o * N[m] * stride + in + l * stride] = tmp[l];
             }
@@ -111,16 +124,16 @@ void or_transform(int d, const int *N, const int *order, const double *vals, dou
  * mode-n products with the vectors (T_l(x_m))_l, last mode first (the
  * evaluation of Section 3.2 with one point per mode).  'work' must hold
  * prod(N)/N[d-1] doubles. */
-double or_eval_point(int d, const int *N, const double *coef, const double *x, double *work)
+real or_eval_point(int d, const int *N, const real *coef, const real *x, real *work)
 {
-    double T[OR_MAXN];
+    real T[OR_MAXN];
     long outer = 1;
     for (int l = 0; l < d - 1; ++l) outer *= N[l];
-    const double *src = coef;
+    const real *src = coef;
     for (int m = d - 1; m >= 0; --m) {
         or_cheb_T(N[m], x[m], T);
         for (long o = 0; o < outer; ++o) {
-            double s = 0.0;
+            real s = 0.0;
             for (int k = 0; k < N[m]; ++k) s += src[o * N[m] + k] * T[k];
             work[o] = s;
         }
@@ -131,13 +144,13 @@ double or_eval_point(int d, const int *N, const double *coef, const double *x, d
 }
 
 /* Series values at npts points x (npts x d, row-major). */
-void or_eval(int d, const int *N, const double *coef, const double *x, long npts, double *out)
+void or_eval(int d, const int *N, const real *coef, const real *x, long npts, real *out)
 {
     long wsz = 1;
     for (int l = 0; l < d - 1; ++l) wsz *= N[l];
     #pragma omp parallel
     {
-        double *work = (double *)malloc(sizeof(double) * (size_t)(wsz > 0 ? wsz : 1));
+        real *work = (real *)malloc(sizeof(real) * (size_t)(wsz > 0 ? wsz : 1));
         #pragma omp for schedule(static)
         for (long q = 0; q < npts; ++q) out[q] = or_eval_point(d, N, coef, x + q * d, work);
         free(work);
@@ -149,24 +162,24 @@ void or_eval(int d, const int *N, const double *coef, const double *x, long npts
  *   q_l = (2 / c_l) sum_{j=l+1..n, j+l odd} j p_j,  c_0 = 2, c_l = 1 (l >= 1).
  * Reading: the printed "2/c_l + sum" is a product "2/c_l * sum"; the interval
  * factor 2/(b-a) is applied by the caller. */
-void or_chebder(int cnt, const double *p, double *q)
+void or_chebder(int cnt, const real *p, real *q)
 {
     int n = cnt - 1;
     for (int l = 0; l < n; ++l) {
-        double s = 0.0;
+        real s = 0.0;
         for (int j = l + 1; j <= n; ++j)
-            if ((j + l) % 2 == 1) s += (double)j * p[j];
+            if ((j + l) % 2 == 1) s += (real)j * p[j];
         q[l] = (l == 0 ? 1.0 : 2.0) * s;
     }
     if (n >= 0) q[n] = 0.0;
 }
 
 /* sum_{l<cnt} q_l T_l(s), with T_l generated by the recurrence. */
-double or_series(int cnt, const double *q, double s)
+real or_series(int cnt, const real *q, real s)
 {
-    double T[OR_MAXN];
+    real T[OR_MAXN];
     or_cheb_T(cnt, s, T);
-    double v = 0.0;
+    real v = 0.0;
     for (int l = 0; l < cnt; ++l) v += q[l] * T[l];
     return v;
 }
@@ -182,39 +195,39 @@ double or_series(int cnt, const double *q, double s)
  * Returns v at the maximiser; *s_star receives the maximiser and *n_crit the
  * number of sign changes of v' seen on the grid (>= 2 flags a non-concave
  * line function). */
-double or_argmax_line(int cnt, const double *q, double *s_star, int *n_crit)
+real or_argmax_line(int cnt, const real *q, real *s_star, int *n_crit)
 {
-    double dq[OR_MAXN];
+    real dq[OR_MAXN];
     or_chebder(cnt, q, dq);
     const int G = 16 * cnt;
-    double best_s = -1.0, best_v = or_series(cnt, q, -1.0);
+    real best_s = -1.0, best_v = or_series(cnt, q, -1.0);
     int ncr = 0;
-    double sa = -1.0, da = or_series(cnt, dq, -1.0);
+    real sa = -1.0, da = or_series(cnt, dq, -1.0);
     int last_sign = (da > 0.0) - (da < 0.0);
     for (int g = 1; g <= G; ++g) {
-        double sb = -1.0 + 2.0 * (double)g / (double)G;
-        double db = or_series(cnt, dq, sb);
+        real sb = -1.0 + 2.0 * (real)g / (real)G;
+        real db = or_series(cnt, dq, sb);
         int sgn = (db > 0.0) - (db < 0.0);
         if (sgn != 0) {
             if (last_sign != 0 && sgn != last_sign) ++ncr;
             last_sign = sgn;
         }
         if (da > 0.0 && db <= 0.0) {
-            double lo = sa, hi = sb;
+            real lo = sa, hi = sb;
             for (int it = 0; it < 200; ++it) {
-                double mid = 0.5 * (lo + hi);
+                real mid = 0.5 * (lo + hi);
                 if (mid <= lo || mid >= hi) break;
                 if (or_series(cnt, dq, mid) > 0.0) lo = mid; else hi = mid;
             }
-            double s = 0.5 * (lo + hi);
-            double v = or_series(cnt, q, s);
-            double tol = 1e-15 * fmax(1.0, fabs(best_v));
+            real s = 0.5 * (lo + hi);
+            real v = or_series(cnt, q, s);
+            real tol = 1e-15 * fmax(1.0, fabs(best_v));
             if (v > best_v + tol) { best_v = v; best_s = s; }
         }
         sa = sb;
         da = db;
     }
-    double v1 = or_series(cnt, q, 1.0);
+    real v1 = or_series(cnt, q, 1.0);
     if (v1 > best_v + 1e-15 * fmax(1.0, fabs(best_v))) { best_v = v1; best_s = 1.0; }
     *s_star = best_s;
     if (n_crit) *n_crit = ncr;
@@ -226,9 +239,9 @@ double or_argmax_line(int cnt, const double *q, double *s_star, int *n_crit)
 
 typedef struct {
     int d, N, Nu;                /* players = state dims; nodes per dim; control nodes */
-    double h, rho, pmax, umax;
-    double K[OR_MAXD * OR_MAXD]; /* exchange matrix, row-major */
-    double m[OR_MAXD], c[OR_MAXD], beta[OR_MAXD], A[OR_MAXD], phi[OR_MAXD];
+    real h, rho, pmax, umax;
+    real K[OR_MAXD * OR_MAXD]; /* exchange matrix, row-major */
+    real m[OR_MAXD], c[OR_MAXD], beta[OR_MAXD], A[OR_MAXD], phi[OR_MAXD];
 } or_game;
 
 /* Drift g(p,u) of Section 2.1.  Reading: the examples' K has a negative
@@ -236,10 +249,10 @@ typedef struct {
  * matrix form g_i = (K p)_i / m_i - c_i p_i + beta_i u_i, which is the
  * diffusive exchange sum_{j != i} k_ij (p_j - p_i) / m_i for zero row sums
  * (a more negative diagonal is leakage to the outside). */
-static void drift(const or_game *g, const double *p, const double *u, double *out)
+static void drift(const or_game *g, const real *p, const real *u, real *out)
 {
     for (int i = 0; i < g->d; ++i) {
-        double s = 0.0;
+        real s = 0.0;
         for (int j = 0; j < g->d; ++j) s += g->K[i * g->d + j] * p[j];
         out[i] = s / g->m[i] - g->c[i] * p[i] + g->beta[i] * u[i];
     }
@@ -247,7 +260,7 @@ static void drift(const or_game *g, const double *p, const double *u, double *ou
 
 /* Instant payoff G_i(p_i, u_i) = u_i (A_i - u_i/2) - phi_i p_i^2 / 2 (LQ
  * specification of Section 2). */
-static double payoff(const or_game *g, int i, double p_i, double u_i)
+static real payoff(const or_game *g, int i, real p_i, real u_i)
 {
     return u_i * (g->A[i] - 0.5 * u_i) - 0.5 * g->phi[i] * p_i * p_i;
 }
@@ -267,15 +280,15 @@ static long ipow(int b, int e) { long r = 1; while (e-- > 0) r *= b; return r; }
  *   - the new control is the global argmax of the fit over [0, U_M] and the
  *     new value is the fit at that control (Step 3, Step 4).
  * 'work' holds N^(d-1) doubles. */
-static void update_node(const or_game *g, int i, long j, const double *coef_i,
-                        const double *U, const double *xnodes, const double *unodes,
-                        double *V_out, double *U_out, int *ncrit, double *work)
+static void update_node(const or_game *g, int i, long j, const real *coef_i,
+                        const real *U, const real *xnodes, const real *unodes,
+                        real *V_out, real *U_out, int *ncrit, real *work)
 {
     int d = g->d, N = g->N, Nu = g->Nu;
     long NN = ipow(N, d);
     int Nd[OR_MAXD];
-    double p[OR_MAXD], ubar[OR_MAXD], b[OR_MAXD], y[OR_MAXD], x[OR_MAXD];
-    double vals[OR_MAXN], q[OR_MAXN];
+    real p[OR_MAXD], ubar[OR_MAXD], b[OR_MAXD], y[OR_MAXD], x[OR_MAXD];
+    real vals[OR_MAXN], q[OR_MAXN];
     long rem = j;
     for (int l = d - 1; l >= 0; --l) {
         int k = (int)(rem % N);
@@ -285,31 +298,31 @@ static void update_node(const or_game *g, int i, long j, const double *coef_i,
     }
     for (int l = 0; l < d; ++l) ubar[l] = U[l * NN + j];
     drift(g, p, ubar, b);
-    double delta = 1.0 - g->rho * g->h; /* delta_h = 1 - rho h (Section 2.1) */
+    real delta = 1.0 - g->rho * g->h; /* delta_h = 1 - rho h (Section 2.1) */
     for (int m = 0; m < Nu; ++m) {
         for (int l = 0; l < d; ++l) y[l] = p[l] + g->h * b[l];
         y[i] += g->h * g->beta[i] * (unodes[m] - ubar[i]);
         for (int l = 0; l < d; ++l) x[l] = 2.0 * y[l] / g->pmax - 1.0;
-        double cont = or_eval_point(d, Nd, coef_i, x, work);
+        real cont = or_eval_point(d, Nd, coef_i, x, work);
         vals[m] = g->h * payoff(g, i, p[i], unodes[m]) + delta * cont;
     }
     or_coef_1d(Nu, vals, 1, q, 1);
-    double s;
-    double v = or_argmax_line(Nu, q, &s, ncrit);
+    real s;
+    real v = or_argmax_line(Nu, q, &s, ncrit);
     *V_out = v;
     *U_out = 0.5 * g->umax * (s + 1.0); /* s in [-1,1] back to u in [0, U_M] */
 }
 
-static void grids(const or_game *g, double *xnodes, double *unodes)
+static void grids(const or_game *g, real *xnodes, real *unodes)
 {
     or_nodes(g->N, xnodes);
-    double su[OR_MAXN];
+    real su[OR_MAXN];
     or_nodes(g->Nu, su);
     for (int m = 0; m < g->Nu; ++m) unodes[m] = 0.5 * g->umax * (su[m] + 1.0);
 }
 
 /* Coefficients of every player's value tensor (Algorithm Cnv per player). */
-static void all_coefs(const or_game *g, const double *V, double *coef)
+static void all_coefs(const or_game *g, const real *V, real *coef)
 {
     int Nd[OR_MAXD];
     for (int l = 0; l < g->d; ++l) Nd[l] = g->N;
@@ -320,21 +333,21 @@ static void all_coefs(const or_game *g, const double *V, double *coef)
 /* One iteration r -> r+1 for every player and node.  V, U, Vn, Un have shape
  * (d, N^d).  Returns max_{i,j} |Vn - V| (the TOL test of Step 4, on the
  * nodes) and the number of (i,j) whose line function is not concave. */
-double or_step(const or_game *g, const double *V, const double *U, double *Vn, double *Un,
+real or_step(const or_game *g, const real *V, const real *U, real *Vn, real *Un,
                long *n_nonconcave)
 {
     int d = g->d;
     long NN = ipow(g->N, d);
-    double xnodes[OR_MAXN], unodes[OR_MAXN];
+    real xnodes[OR_MAXN], unodes[OR_MAXN];
     grids(g, xnodes, unodes);
-    double *coef = (double *)malloc(sizeof(double) * (size_t)(d * NN));
+    real *coef = (real *)malloc(sizeof(real) * (size_t)(d * NN));
     all_coefs(g, V, coef);
-    double res = 0.0;
+    real res = 0.0;
     long nnc = 0;
     long wsz = NN / g->N;
     #pragma omp parallel reduction(max:res) reduction(+:nnc)
     {
-        double *work = (double *)malloc(sizeof(double) * (size_t)(wsz > 0 ? wsz : 1));
+        real *work = (real *)malloc(sizeof(real) * (size_t)(wsz > 0 ? wsz : 1));
         #pragma omp for schedule(dynamic, 16)
         for (long t = 0; t < d * NN; ++t) {
             int i = (int)(t / NN);
@@ -342,7 +355,7 @@ double or_step(const or_game *g, const double *V, const double *U, double *Vn, d
             int ncr = 0;
             update_node(g, i, j, coef + i * NN, U, xnodes, unodes, Vn + t, Un + t, &ncr, work);
             if (ncr >= 2) ++nnc;
-            double e = fabs(Vn[t] - V[t]);
+            real e = fabs(Vn[t] - V[t]);
             if (e > res) res = e;
         }
         free(work);
@@ -354,19 +367,19 @@ double or_step(const or_game *g, const double *V, const double *U, double *Vn, d
 
 /* The same update for a list of (player, node) pairs only: used to check
  * large grids on sampled outputs. */
-void or_step_sample(const or_game *g, const double *V, const double *U, long count,
-                    const int *players, const long *nodes, double *Vn, double *Un)
+void or_step_sample(const or_game *g, const real *V, const real *U, long count,
+                    const int *players, const long *nodes, real *Vn, real *Un)
 {
     int d = g->d;
     long NN = ipow(g->N, d);
-    double xnodes[OR_MAXN], unodes[OR_MAXN];
+    real xnodes[OR_MAXN], unodes[OR_MAXN];
     grids(g, xnodes, unodes);
-    double *coef = (double *)malloc(sizeof(double) * (size_t)(d * NN));
+    real *coef = (real *)malloc(sizeof(real) * (size_t)(d * NN));
     all_coefs(g, V, coef);
     long wsz = NN / g->N;
     #pragma omp parallel
     {
-        double *work = (double *)malloc(sizeof(double) * (size_t)(wsz > 0 ? wsz : 1));
+        real *work = (real *)malloc(sizeof(real) * (size_t)(wsz > 0 ? wsz : 1));
         #pragma omp for schedule(dynamic, 1)
         for (long t = 0; t < count; ++t) {
             int ncr;
@@ -382,17 +395,17 @@ void or_step_sample(const or_game *g, const double *V, const double *U, long cou
  * drops below tol (strict, Step 4) when tol > 0.  V and U are updated in
  * place; residuals[r] receives the residual of iteration r.  Returns the
  * number of iterations done. */
-int or_solve(const or_game *g, double *V, double *U, int steps, double tol, double *residuals)
+int or_solve(const or_game *g, real *V, real *U, int steps, real tol, real *residuals)
 {
     long n = (long)g->d * ipow(g->N, g->d);
-    double *Vn = (double *)malloc(sizeof(double) * (size_t)n);
-    double *Un = (double *)malloc(sizeof(double) * (size_t)n);
+    real *Vn = (real *)malloc(sizeof(real) * (size_t)n);
+    real *Un = (real *)malloc(sizeof(real) * (size_t)n);
     int r;
     for (r = 0; r < steps; ++r) {
         long nnc;
-        double res = or_step(g, V, U, Vn, Un, &nnc);
-        memcpy(V, Vn, sizeof(double) * (size_t)n);
-        memcpy(U, Un, sizeof(double) * (size_t)n);
+        real res = or_step(g, V, U, Vn, Un, &nnc);
+        memcpy(V, Vn, sizeof(real) * (size_t)n);
+        memcpy(U, Un, sizeof(real) * (size_t)n);
         if (residuals) residuals[r] = res;
         if (tol > 0.0 && res < tol) { ++r; break; }
     }
@@ -410,21 +423,21 @@ int or_solve(const or_game *g, double *V, double *U, int steps, double tol, doub
  * iteration assumes (Section 2.1), and the interpolant of controls that sit
  * on the bounds can leave [0, U_M] between nodes, hence the clip.
  * U has shape (d, N^d); paths (n_steps+1) x d; controls n_steps x d. */
-void or_simulate(const or_game *g, const double *U, const double *p0, int n_steps, double *paths,
-                 double *controls)
+void or_simulate(const or_game *g, const real *U, const real *p0, int n_steps, real *paths,
+                 real *controls)
 {
     int d = g->d, Nd[OR_MAXD];
     for (int l = 0; l < d; ++l) Nd[l] = g->N;
     long NN = ipow(g->N, d);
-    double *coef = (double *)malloc(sizeof(double) * (size_t)(d * NN));
-    double *work = (double *)malloc(sizeof(double) * (size_t)(NN / g->N > 0 ? NN / g->N : 1));
+    real *coef = (real *)malloc(sizeof(real) * (size_t)(d * NN));
+    real *work = (real *)malloc(sizeof(real) * (size_t)(NN / g->N > 0 ? NN / g->N : 1));
     for (int i = 0; i < d; ++i) or_transform(d, Nd, NULL, U + i * NN, coef + i * NN);
-    double p[OR_MAXD], u[OR_MAXD], x[OR_MAXD], b[OR_MAXD];
+    real p[OR_MAXD], u[OR_MAXD], x[OR_MAXD], b[OR_MAXD];
     for (int l = 0; l < d; ++l) p[l] = paths[l] = p0[l];
     for (int n = 0; n < n_steps; ++n) {
         for (int l = 0; l < d; ++l) x[l] = 2.0 * p[l] / g->pmax - 1.0;
         for (int i = 0; i < d; ++i) {
-            double v = or_eval_point(d, Nd, coef + i * NN, x, work);
+            real v = or_eval_point(d, Nd, coef + i * NN, x, work);
             u[i] = v < 0.0 ? 0.0 : (v > g->umax ? g->umax : v);
             if (controls) controls[n * d + i] = u[i];
         }
@@ -448,7 +461,7 @@ typedef struct {
     int d;
     int Np[OR_MAXD];   /* Lobatto nodes of each state dimension */
     int Nu[OR_MAXD];   /* control nodes of each player on [0, U_M] */
-    double h, rho, pmax, umax;
+    real h, rho, pmax, umax;
 } or_gen;
 
 /* Update of every player at state node j (Steps 1-4 of the generalised
@@ -469,15 +482,15 @@ typedef struct {
  * coefV holds the coefficient tensors of V^{[r]} ([d][N_P]), U the controls
  * u^{[r]} ([d][N_P]); vn, un receive the d new values and controls of node
  * j.  'ctl' holds 2 d prod(Nu) doubles, 'work' max(prod(Np), prod(Nu)). */
-static void gen_node(const or_gen *g, long j, const double *gvals, const double *pvals,
-                     const double *coefV, const double *U, double xn[][OR_MAXN],
-                     double un[][OR_MAXN], double *vn, double *un_out, double *ctl, double *work)
+static void gen_node(const or_gen *g, long j, const real *gvals, const real *pvals,
+                     const real *coefV, const real *U, real xn[][OR_MAXN],
+                     real un[][OR_MAXN], real *vn, real *un_out, real *ctl, real *work)
 {
     int d = g->d;
     long NP = 1, UP = 1;
     for (int l = 0; l < d; ++l) { NP *= g->Np[l]; UP *= g->Nu[l]; }
-    double p[OR_MAXD], ubar[OR_MAXD], u[OR_MAXD], yv[OR_MAXD], x[OR_MAXD], gd[OR_MAXD];
-    double vals[OR_MAXN], q[OR_MAXN];
+    real p[OR_MAXD], ubar[OR_MAXD], u[OR_MAXD], yv[OR_MAXD], x[OR_MAXD], gd[OR_MAXD];
+    real vals[OR_MAXN], q[OR_MAXN];
     long rem = j;
     for (int l = d - 1; l >= 0; --l) {
         int k = (int)(rem % g->Np[l]);
@@ -490,7 +503,7 @@ static void gen_node(const or_gen *g, long j, const double *gvals, const double 
         or_transform(d, g->Nu, NULL, gvals + ((long)k * NP + j) * UP, ctl + (long)k * UP);
         or_transform(d, g->Nu, NULL, pvals + ((long)k * NP + j) * UP, ctl + (long)(d + k) * UP);
     }
-    double delta = 1.0 - g->rho * g->h;
+    real delta = 1.0 - g->rho * g->h;
     for (int i = 0; i < d; ++i) {
         int nu = g->Nu[i];
         for (int m = 0; m < nu; ++m) {
@@ -498,13 +511,13 @@ static void gen_node(const or_gen *g, long j, const double *gvals, const double 
             u[i] = un[i][m];
             for (int l = 0; l < d; ++l) yv[l] = 2.0 * u[l] / g->umax - 1.0;
             for (int k = 0; k < d; ++k) gd[k] = or_eval_point(d, g->Nu, ctl + (long)k * UP, yv, work);
-            double G = or_eval_point(d, g->Nu, ctl + (long)(d + i) * UP, yv, work);
+            real G = or_eval_point(d, g->Nu, ctl + (long)(d + i) * UP, yv, work);
             for (int l = 0; l < d; ++l) x[l] = 2.0 * (p[l] + g->h * gd[l]) / g->pmax - 1.0;
-            double cont = or_eval_point(d, g->Np, coefV + (long)i * NP, x, work);
+            real cont = or_eval_point(d, g->Np, coefV + (long)i * NP, x, work);
             vals[m] = g->h * G + delta * cont;
         }
         or_coef_1d(nu, vals, 1, q, 1);
-        double s;
+        real s;
         vn[i] = or_argmax_line(nu, q, &s, NULL);
         un_out[i] = 0.5 * g->umax * (s + 1.0);
     }
@@ -513,28 +526,28 @@ static void gen_node(const or_gen *g, long j, const double *gvals, const double 
 /* Update of the listed nodes (every node when nodes == NULL, count = N_P).
  * V, U are [d][N_P]; Vn, Un receive [d][count].  Returns the largest
  * |Vn - V| over the listed nodes (the TOL test of Step 4 when all are). */
-static double gen_update(const or_gen *g, const double *gvals, const double *pvals, const double *V,
-                         const double *U, long count, const long *nodes, double *Vn, double *Un)
+static real gen_update(const or_gen *g, const real *gvals, const real *pvals, const real *V,
+                         const real *U, long count, const long *nodes, real *Vn, real *Un)
 {
     int d = g->d;
     long NP = 1, UP = 1;
     for (int l = 0; l < d; ++l) { NP *= g->Np[l]; UP *= g->Nu[l]; }
-    double xn[OR_MAXD][OR_MAXN], un[OR_MAXD][OR_MAXN];
+    real xn[OR_MAXD][OR_MAXN], un[OR_MAXD][OR_MAXN];
     for (int l = 0; l < d; ++l) {
         or_nodes(g->Np[l], xn[l]);
-        double su[OR_MAXN];
+        real su[OR_MAXN];
         or_nodes(g->Nu[l], su);
         for (int m = 0; m < g->Nu[l]; ++m) un[l][m] = 0.5 * g->umax * (su[m] + 1.0);
     }
-    double *coefV = (double *)malloc(sizeof(double) * (size_t)(d * NP));
+    real *coefV = (real *)malloc(sizeof(real) * (size_t)(d * NP));
     for (int i = 0; i < d; ++i) or_transform(d, g->Np, NULL, V + i * NP, coefV + i * NP);
     long wsz = NP > UP ? NP : UP;
-    double res = 0.0;
+    real res = 0.0;
     #pragma omp parallel reduction(max:res)
     {
-        double *ctl = (double *)malloc(sizeof(double) * (size_t)(2 * d * UP));
-        double *work = (double *)malloc(sizeof(double) * (size_t)wsz);
-        double vn[OR_MAXD], unn[OR_MAXD];
+        real *ctl = (real *)malloc(sizeof(real) * (size_t)(2 * d * UP));
+        real *work = (real *)malloc(sizeof(real) * (size_t)wsz);
+        real vn[OR_MAXD], unn[OR_MAXD];
         #pragma omp for schedule(dynamic, 4)
         for (long t = 0; t < count; ++t) {
             long j = nodes ? nodes[t] : t;
@@ -542,7 +555,7 @@ static double gen_update(const or_gen *g, const double *gvals, const double *pva
             for (int i = 0; i < d; ++i) {
                 Vn[(long)i * count + t] = vn[i];
                 Un[(long)i * count + t] = unn[i];
-                double e = fabs(vn[i] - V[(long)i * NP + j]);
+                real e = fabs(vn[i] - V[(long)i * NP + j]);
                 if (!(e <= res)) res = e; /* a NaN wins */
             }
         }
@@ -555,8 +568,8 @@ static double gen_update(const or_gen *g, const double *gvals, const double *pva
 
 /* One iteration of the generalised algorithm on every node: V, U, Vn, Un
  * are [d][N_P]; gvals, pvals [d][N_P][prod(Nu)].  Returns max |Vn - V|. */
-double or_gen_step(const or_gen *g, const double *gvals, const double *pvals, const double *V,
-                   const double *U, double *Vn, double *Un)
+real or_gen_step(const or_gen *g, const real *gvals, const real *pvals, const real *V,
+                   const real *U, real *Vn, real *Un)
 {
     long NP = 1;
     for (int l = 0; l < g->d; ++l) NP *= g->Np[l];
@@ -565,8 +578,8 @@ double or_gen_step(const or_gen *g, const double *gvals, const double *pvals, co
 
 /* The same update at the listed nodes only (every player of each); Vn, Un
  * receive [d][count].  Used to check large grids on sampled outputs. */
-void or_gen_step_sample(const or_gen *g, const double *gvals, const double *pvals, const double *V,
-                        const double *U, long count, const long *nodes, double *Vn, double *Un)
+void or_gen_step_sample(const or_gen *g, const real *gvals, const real *pvals, const real *V,
+                        const real *U, long count, const long *nodes, real *Vn, real *Un)
 {
     gen_update(g, gvals, pvals, V, U, count, nodes, Vn, Un);
 }

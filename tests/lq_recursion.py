@@ -24,12 +24,12 @@ import numpy as np
 
 
 class LQState:
-    def __init__(self, d: int):
-        self.Q = np.zeros((d, d, d))
-        self.q = np.zeros((d, d))
-        self.s = np.zeros(d)
-        self.a = np.zeros(d)
-        self.f = np.zeros((d, d))
+    def __init__(self, d: int, dtype=np.float64):
+        self.Q = np.zeros((d, d, d), dtype=dtype)
+        self.q = np.zeros((d, d), dtype=dtype)
+        self.s = np.zeros(d, dtype=dtype)
+        self.a = np.zeros(d, dtype=dtype)
+        self.f = np.zeros((d, d), dtype=dtype)
 
     def value(self, i: int, P: np.ndarray) -> np.ndarray:
         """V_i at the rows of P (n x d)."""
@@ -39,32 +39,35 @@ class LQState:
         return self.a[i] + P @ self.f[i]
 
 
-def lq_iterate(game, steps: int):
-    """Yield the LQState after each of ``steps`` iterations from V = 0, u = A."""
-    K = np.asarray(game.K, dtype=np.float64)
-    m = np.asarray(game.m, dtype=np.float64)
-    M = K / m[:, None] - np.diag(game.c)
-    B = np.diag(np.asarray(game.beta, dtype=np.float64))
-    yield from lq_iterate_mats(M, B, game.A, game.phi, game.h, game.rho, game.A, steps)
+def lq_iterate(game, steps: int, dtype=np.float64):
+    """Yield the LQState after each of ``steps`` iterations from V = 0, u = A
+    (arithmetic in ``dtype``: float64, or np.longdouble)."""
+    K = np.asarray(game.K, dtype=dtype)
+    m = np.asarray(game.m, dtype=dtype)
+    M = K / m[:, None] - np.diag(np.asarray(game.c, dtype=dtype))
+    B = np.diag(np.asarray(game.beta, dtype=dtype))
+    yield from lq_iterate_mats(M, B, game.A, game.phi, game.h, game.rho, game.A, steps, dtype=dtype)
 
 
-def lq_iterate_mats(M, B, A, phi, h: float, rho: float, a0, steps: int):
+def lq_iterate_mats(M, B, A, phi, h: float, rho: float, a0, steps: int, dtype=np.float64):
     """The same recursion for the drift g = M p + B u with a full emission
     matrix B (column l: how player l's emissions enter every stock), which
     makes the game non-separable in the controls: the frozen controls of the
     other players shift every component of the update point.  Starts from
     V = 0 and the constant controls a0."""
-    M, B = np.asarray(M, dtype=np.float64), np.asarray(B, dtype=np.float64)
+    M, B = np.asarray(M, dtype=dtype), np.asarray(B, dtype=dtype)
+    A, phi = np.asarray(A, dtype=dtype), np.asarray(phi, dtype=dtype)
+    h, rho = dtype(h), dtype(rho)
     d = M.shape[0]
-    delta = 1.0 - rho * h
-    I = np.eye(d)
-    st = LQState(d)
-    st.a = np.asarray(a0, dtype=np.float64).copy()
+    delta = 1 - rho * h
+    I = np.eye(d, dtype=dtype)
+    st = LQState(d, dtype)
+    st.a = np.asarray(a0, dtype=dtype).copy()
     for _ in range(steps):
-        nx = LQState(d)
+        nx = LQState(d, dtype)
         for i in range(d):
             E = I + h * M
-            e0 = np.zeros(d)
+            e0 = np.zeros(d, dtype=dtype)
             for l in range(d):
                 if l != i:
                     E = E + h * np.outer(B[:, l], st.f[l])
@@ -84,20 +87,21 @@ def lq_iterate_mats(M, B, A, phi, h: float, rho: float, a0, steps: int):
         yield st
 
 
-def node_points(game) -> np.ndarray:
+def node_points(game, dtype=np.float64) -> np.ndarray:
     """Physical node coordinates (N^d x d), C order, index 0 = p_max."""
     n = game.N - 1
-    x = np.cos(np.pi * np.arange(game.N) / n)
-    p1 = 0.5 * game.p_max * (x + 1.0)
+    pi = np.arccos(dtype(-1))
+    x = np.cos(pi * np.arange(game.N, dtype=dtype) / dtype(n))
+    p1 = dtype(0.5) * dtype(game.p_max) * (x + 1)
     grids = np.meshgrid(*([p1] * game.d), indexing="ij")
     return np.stack([g.ravel() for g in grids], axis=1)
 
 
-def lq_nodal(game, steps: int):
+def lq_nodal(game, steps: int, dtype=np.float64):
     """(V, U) at the nodes after ``steps`` iterations, each (d, N^d)."""
-    P = node_points(game)
+    P = node_points(game, dtype)
     st = None
-    for st in lq_iterate(game, steps):
+    for st in lq_iterate(game, steps, dtype):
         pass
     V = np.stack([st.value(i, P) for i in range(game.d)])
     U = np.stack([st.control(i, P) for i in range(game.d)])
