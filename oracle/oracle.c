@@ -188,10 +188,13 @@ real or_series(int cnt, const real *q, real s)
  * Reading: the paper asks for the argmax over the admissible controls and
  * recommends Newton's method without a start, a stopping rule or a rule for
  * the constraint.  The oracle takes the plain definition instead: the
- * candidates are both endpoints and every interior local maximum of v, found
- * where v' changes sign from + to - on a uniform grid of 16*cnt intervals and
- * refined by bisection of v' down to adjacent doubles; the largest v wins and
- * a tie (within 1e-15 max(1,|v|)) goes to the smaller s.
+ * candidates are the local maxima of v on [-1,1], that is an endpoint where
+ * v' points out of the interval (v'(-1) <= 0, v'(+1) >= 0) and every interior
+ * point where v' changes sign from + to -, found on a uniform grid of 16*cnt
+ * intervals and refined by bisection of v' down to adjacent doubles; the
+ * largest v wins and a tie (within 1e-15 max(1,|v|)) goes to the smaller s.
+ * An endpoint where v still increases into the interval is no maximiser, so
+ * it is no candidate however close its value comes to the interior maximum.
  * Returns v at the maximiser; *s_star receives the maximiser and *n_crit the
  * number of sign changes of v' seen on the grid (>= 2 flags a non-concave
  * line function). */
@@ -200,10 +203,11 @@ real or_argmax_line(int cnt, const real *q, real *s_star, int *n_crit)
     real dq[OR_MAXN];
     or_chebder(cnt, q, dq);
     const int G = 16 * cnt;
-    real best_s = -1.0, best_v = or_series(cnt, q, -1.0);
     int ncr = 0;
     real sa = -1.0, da = or_series(cnt, dq, -1.0);
     int last_sign = (da > 0.0) - (da < 0.0);
+    int have = da <= 0.0; /* the left endpoint is a local maximum */
+    real best_s = -1.0, best_v = have ? or_series(cnt, q, -1.0) : 0.0;
     for (int g = 1; g <= G; ++g) {
         real sb = -1.0 + 2.0 * (real)g / (real)G;
         real db = or_series(cnt, dq, sb);
@@ -221,14 +225,19 @@ real or_argmax_line(int cnt, const real *q, real *s_star, int *n_crit)
             }
             real s = 0.5 * (lo + hi);
             real v = or_series(cnt, q, s);
-            real tol = 1e-15 * fmax(1.0, fabs(best_v));
-            if (v > best_v + tol) { best_v = v; best_s = s; }
+            if (!have || v > best_v + 1e-15 * fmax(1.0, fabs(best_v))) { best_v = v; best_s = s; have = 1; }
         }
         sa = sb;
         da = db;
     }
-    real v1 = or_series(cnt, q, 1.0);
-    if (v1 > best_v + 1e-15 * fmax(1.0, fabs(best_v))) { best_v = v1; best_s = 1.0; }
+    if (da >= 0.0) { /* the right endpoint is a local maximum */
+        real v1 = or_series(cnt, q, 1.0);
+        if (!have || v1 > best_v + 1e-15 * fmax(1.0, fabs(best_v))) { best_v = v1; best_s = 1.0; have = 1; }
+    }
+    if (!have) { /* only when v' is not a number: let it reach the value */
+        best_s = -1.0;
+        best_v = or_series(cnt, q, -1.0) + da;
+    }
     *s_star = best_s;
     if (n_crit) *n_crit = ncr;
     return best_v;

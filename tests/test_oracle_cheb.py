@@ -243,6 +243,20 @@ def test_argmax_concave_quadratic(orc):
         assert abs(s - s0) < 1e-12 and abs(v) < 1e-15 and nc == 1
 
 
+def test_argmax_interior_maximum_next_to_an_endpoint(orc):
+    # v(s) = -(s - s0)^2 with s0 = -1 + 1e-8: the fit still rises at s = -1
+    # (v'(-1) = 2e-8 > 0), so -1 is no maximiser even though v(-1) = -1e-16
+    # lies within any value tolerance of the maximum v(s0) = 0
+    for s0 in (-1 + 1e-8, -1 + 3.6e-7, 1 - 1e-8):
+        q = np.array([-(0.5 + s0 * s0), 2 * s0, -0.5])
+        s, v, nc = orc.argmax_line(q)
+        assert abs(s - s0) < 1e-12 and abs(v) < 1e-15 and nc == 1
+    # an endpoint whose derivative points outward stays the maximiser
+    q = np.array([-(0.5 + 1.0), -2.0, -0.5])     # -(s + 1)^2: v'(-1) = 0, maximum at -1
+    s, v, _ = orc.argmax_line(q)
+    assert s == -1.0
+
+
 def test_argmax_boundary_and_global(orc):
     s, v, _ = orc.argmax_line(np.array([0.0, 1.0, 0.0]))       # v = s: max at +1
     assert s == 1.0 and v == 1.0
