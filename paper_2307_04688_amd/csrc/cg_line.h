@@ -88,9 +88,12 @@ __device__ __forceinline__ bool certainly_concave(const double (&q)[NW])
 // recommends Newton's method on v').  Strictly concave lines (the usual case)
 // take the endpoint whose one-sided derivative points outward, or a
 // bracketed Newton iteration on v' started at s0.  Other lines take the
-// global maximum over both endpoints and every sign change + to - of v' on a
-// uniform grid of 16 n intervals (n = number of control nodes), refined by
-// bisection; ties go to the smaller s.  Returns v(s*) and stores s*.
+// global maximum over their local maxima: an endpoint whose one-sided
+// derivative points outward and every sign change + to - of v' on a uniform
+// grid of 16 n intervals (n = number of control nodes), refined by
+// bisection; ties go to the smaller s.  An endpoint where v still rises into
+// the interval is no candidate, however close its value.  Returns v(s*) and
+// stores s*.
 template <int NW>
 __device__ double line_argmax(const double (&q)[NW], int n, double s0, double &s_out)
 {
@@ -132,9 +135,10 @@ __device__ double line_argmax(const double (&q)[NW], int n, double s0, double &s
         }
     } else {
         const int G = 16 * n;
-        double best_s = -1.0, best_v = clenshaw(q, -1.0);
         double f, f1a, f2;
         clenshaw3(q, -1.0, f, f1a, f2);
+        bool have = f1a <= 0.0;  // the left endpoint is a local maximum
+        double best_s = -1.0, best_v = have ? clenshaw(q, -1.0) : 0.0;
         double sa = -1.0;
         for (int g = 1; g <= G; ++g) {
             const double sb = -1.0 + 2.0 * (double)g / (double)G;
@@ -151,14 +155,20 @@ __device__ double line_argmax(const double (&q)[NW], int n, double s0, double &s
                 }
                 const double sc = 0.5 * (lo + hi);
                 const double v = clenshaw(q, sc);
-                if (v > best_v + 1e-15 * fmax(1.0, fabs(best_v))) { best_v = v; best_s = sc; }
+                if (!have || v > best_v + 1e-15 * fmax(1.0, fabs(best_v))) {
+                    best_v = v;
+                    best_s = sc;
+                    have = true;
+                }
             }
             sa = sb;
             f1a = f1b;
         }
-        const double v1 = clenshaw(q, 1.0);
-        if (v1 > best_v + 1e-15 * fmax(1.0, fabs(best_v))) best_s = 1.0;
-        s = best_s;
+        if (f1a >= 0.0) {  // the right endpoint is a local maximum
+            const double v1 = clenshaw(q, 1.0);
+            if (!have || v1 > best_v + 1e-15 * fmax(1.0, fabs(best_v))) best_s = 1.0;
+        }
+        s = best_s;  // -1 when v' is not a number (no candidate)
     }
     s_out = s;
     return clenshaw(q, s);

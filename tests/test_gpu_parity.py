@@ -271,19 +271,13 @@ def test_lq_recursion_full_size_c2(cg):
 
 def test_c2_workload_against_oracle_reference(cg):
     """200 steps of the d=3, N=32 workload against the committed oracle run
-    (512 sampled (player, node) pairs at 9 snapshots).
-
-    Before the control bound u >= 0 binds anywhere (steps <= 50) the FP64 bar
-    holds: V within 1e-12 of max|V|, u within 1e-10 u_max.  Once it binds,
-    the oracle's decision at the bound rests on v'(-1) = sum_l (-1)^(l+1) l^2 q_l
-    with q from the DCT of the line samples, whose rounding (eps |V| per
-    coefficient) is amplified by l^2 <= (N-1)^2: near the switch to u = 0 its
-    maximiser moves by up to ~eps N^3 |V| / (3 |v''|), with |v''| >= h u_max^2/4,
-    i.e. ~1e-10 in s, and those u feed the other players' drift in later
-    steps.  The GPU path computes the same fit coefficients without the
-    sampling round-off.  The bar there is V within 1e-10 of max|V| and u within
-    1e-9 u_max; one-step parity from identical inputs stays at 1e-12 (tested
-    above, also at this size)."""
+    (512 sampled (player, node) pairs at 9 snapshots), at the FP64 bar
+    throughout, also after the control bound u >= 0 starts to bind (from
+    about step 50): V within 1e-12 of max|V|, u within 1e-10 u_max (the
+    maximiser is a root of v', resolved to ~1e-11 in binary64), and the same
+    number of clipped controls over the whole grid.  The oracle's binary64 run
+    itself stays within 1e-13 of its long double run on this workload
+    (test_oracle_extended)."""
     path = os.path.join(GOLD, "c2_oracle_reference.json")
     ref = json.load(open(path))
     g = W.config_game("C2")
@@ -291,6 +285,7 @@ def test_c2_workload_against_oracle_reference(cg):
     G = _gpu_game(cg, g)
     pl, nd = np.array(ref["players"]), np.array(ref["nodes"])
     done = 0
+    clip_seen = False
     for s in sorted(int(k) for k in ref["snapshots"]):
         G.step(s - done)
         done = s
@@ -298,14 +293,15 @@ def test_c2_workload_against_oracle_reference(cg):
         V, U = V.cpu().numpy(), U.cpu().numpy()
         snap = ref["snapshots"][str(s)]
         vmax = ref["vmax"][s - 1]
-        clip_seen = any(ref["snapshots"][k]["clipped"] > 0 for k in ref["snapshots"] if int(k) <= s)
-        tv, tu = (1e-10, 1e-9) if clip_seen else (1e-12, 1e-10)
+        clip_seen = clip_seen or snap["clipped"] > 0
         ev = np.max(np.abs(V[pl, nd] - np.array(snap["V"]))) / vmax
         eu = np.max(np.abs(U[pl, nd] - np.array(snap["U"]))) / g.u_max
-        say(f"  step {s}: rel V {ev:.2e} u {eu:.2e} (bounds {tv:.0e}, {tu:.0e})")
-        assert ev <= tv and eu <= tu, s
-        assert abs(np.max(np.abs(V)) - vmax) <= tv * vmax
-        assert np.count_nonzero(U == 0.0) == snap["clipped"] or clip_seen
+        nclip = int(np.count_nonzero(U == 0.0))
+        say(f"  step {s}: rel V {ev:.2e} u {eu:.2e} clipped {nclip} (oracle {snap['clipped']})")
+        assert ev <= 1e-12 and eu <= 1e-10, s
+        assert abs(np.max(np.abs(V)) - vmax) <= 1e-12 * vmax
+        assert nclip == snap["clipped"], s
+    assert clip_seen  # the bound binds within the run
 
 
 def test_solve_tolerance_matches_oracle(cg, orc):
