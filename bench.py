@@ -290,38 +290,89 @@ def stalled(r, r_prev, tol):
     return r > 0.9 * r_prev and r > 100.0 * tol
 
 
+def lobatto_grid(d: int, N: int):
+    """Normalised coordinates of the N^d Chebyshev-Lobatto nodes in the
+    library's state order (C order, index 0 at x = +1): shape (N^d, d)."""
+    import numpy as np
+    x = np.cos(np.pi * np.arange(N) / (N - 1))
+    return np.stack(np.meshgrid(*([x] * d), indexing="ij"), -1).reshape(-1, d)
+
+
+def interpolate_state(cg, torch, V, U, d: int, Nc: int, Xf, u_max: float):
+    """The degree-(Nc-1) interpolants of a coarse state (V, U of shape
+    (d, Nc^d)) evaluated at the fine grid's nodes Xf, by the library's
+    transform and FP64 evaluation; controls clipped to [0, u_max]."""
+    out = []
+    for A in (V, U):
+        coef = cg.chebyshev_transform(A.reshape((d,) + (Nc,) * d), d=d)
+        out.append(torch.stack([cg.chebyshev_eval(coef[i], Xf, cg.FP64) for i in range(d)]))
+    return out[0], torch.clamp(out[1], 0.0, u_max)
+
+
 def run_warm(cg, W, torch, n_train: int = 4096, n_test: int = 64, N: int = 24, train_tol: float = 1e-7,
-             tol: float = 1e-8, max_steps: int = 100000, train_N: int = 12, train_steps: int = 40000,
+             tol: float = 1e-8, max_steps: int = 100000, coarse_N: int = 12, train_steps: int = 40000,
              slots: int = 32, chunk: int = 500):
     """Learned warm start on d=3 games (seed 5): the network is trained on
-    `n_train` games solved by the method (batched, FP32 MFMA + FP64
-    correction, to residual `train_tol`) on a train_N grid (the network takes
-    node coordinates, so it is then evaluated at the held-out games' N-grid
-    nodes), then `n_test` held-out games are
-    solved to residual `tol` (a) plainly: FP64, one at a time, from zero, and
-    (b) in the chosen form: FP32 MFMA + FP64 correction, from the network's
-    start, batched as a stream through `slots` batch slots (a finished game's
-    slot takes the next game), with the plain zero start as fallback for any
-    game whose warm start or warm iteration is not finite.  The iteration contracts at
-    rate 1 - rho h, so a game with rho near the bottom of its range (0.05)
-    needs ~37 000 iterations to 1e-8: max_steps leaves room for it."""
+    `n_train` N-grid games solved by the method (batched, FP32 MFMA + FP64
+    correction, to residual `train_tol` at N), then `n_test` held-out games
+    are solved to residual `tol` (a) plainly: FP64, one at a time, from zero,
+    and (b) in the chosen form: FP32 MFMA + FP64 correction, from the
+    network's start, batched as a stream through `slots` batch slots (a
+    finished game's slot takes the next game), with the plain zero start as
+    fallback for any game whose warm start or warm iteration is not finite.
+    The training games are solved coarse to fine: to `train_tol` on the
+    coarse_N grid, then that solution's interpolant is the starting iterate
+    of the same game on the N grid, iterated there to `train_tol`
+    (coarse_N = 0: from zero on the N grid).  The iteration contracts at rate
+    1 - rho h, so a game with rho near the bottom of its range (0.05) needs
+    ~37 000 iterations to 1e-8 from zero: max_steps leaves room for it."""
     import numpy as np
     log = lambda *a: print("bench:", *a, file=sys.stderr, flush=True)
-    # the network takes node coordinates, so its training games may use a coarser grid
-    train = [W.make_game(3, train_N or N, seed=5, instance=i) for i in range(n_train)]
-    test = [W.make_game(3, N, seed=5, instance=100000 + i) for i in range(n_test)]
+
+    def batch_solve(handles, what):
+        """Batched solve to train_tol; stops when every game is done
+        (converged or not finite) or when no game has finished for 4000
+        iterations (the rest neither converge nor blow up: excluded)."""
+        B = cg.ChebBatch(handles)
+        res = np.full(len(handles), np.inf)
+        iters, n_done, idle = 0, -1, 0
+        for chunk_ in range(40000 // 2000):
+            _, steps, res = B.solve(2000, train_tol)
+            iters += int(steps.max())
+            done = ~np.isfinite(res) | (res < train_tol)
+            log(f"{what}: {iters} iterations, {int(done.sum())}/{len(handles)} games done")
+            if done.all():
+                break
+            idle = idle + 1 if int(done.sum()) == n_done else 0
+            n_done = int(done.sum())
+            if idle >= 2:
+                break
+        B.destroy()
+        return np.isfinite(res) & (res < train_tol), iters
+
     t0 = time.perf_counter()
-    hs = [cg.ChebGame(g, cg.FP32_CORR) for g in train]
-    B = cg.ChebBatch(hs)
-    for chunk in range(40000 // 2000):
-        _, _, res = B.solve(2000, train_tol)
-        done = ~np.isfinite(res) | (res < train_tol)
-        log(f"training data: {2000 * (chunk + 1)} iterations, {int(done.sum())}/{n_train} games done")
-        if done.all():
-            break
+    coarse_iters = fine_iters = 0
+    if coarse_N:
+        trc = [W.make_game(3, coarse_N, seed=5, instance=i) for i in range(n_train)]
+        hc = [cg.ChebGame(g, cg.FP32_CORR) for g in trc]
+        ok_c, coarse_iters = batch_solve(hc, f"training data, N={coarse_N}")
+        Xf = torch.from_numpy(lobatto_grid(3, N)).cuda()
+    train, hs = [], []
+    for i in range(n_train):
+        g = W.make_game(3, N, seed=5, instance=i)
+        h = cg.ChebGame(g, cg.FP32_CORR)
+        if coarse_N:
+            if ok_c[i]:
+                Vc, Uc, _ = hc[i].get_state()
+                h.set_state(*interpolate_state(cg, torch, Vc, Uc, 3, coarse_N, Xf, g.u_max))
+            hc[i].destroy()
+        train.append(g)
+        hs.append(h)
+    good, fine_iters = batch_solve(hs, f"training data, N={N}")
+    test = [W.make_game(3, N, seed=5, instance=100000 + i) for i in range(n_test)]
+    torch.cuda.synchronize()
     t_data = time.perf_counter() - t0
-    good = np.isfinite(res) & (res < train_tol)
-    log(f"training data: {int(good.sum())}/{n_train} games converged in {t_data:.1f} s")
+    log(f"training data: {int(good.sum())}/{n_train} games converged at N={N} in {t_data:.1f} s")
     Xs, Ts = [], []
     for g, h, ok in zip(train, hs, good):
         if ok:
@@ -443,17 +494,19 @@ def run_warm(cg, W, torch, n_train: int = 4096, n_test: int = 64, N: int = 24, t
             Bw = cg.ChebBatch([hw[s_] for s_ in live])
     torch.cuda.synchronize()
     t_warm = time.perf_counter() - t0
-    errs = []
+    errs, err_rho = [], []
     for k in range(n_test):
         if Vref[k] is not None and Vwarm[k] is not None:
             V = Vwarm[k]
             errs.append((torch.max(torch.abs(V - Vref[k])) / torch.max(torch.abs(Vref[k]))).item())
+            err_rho.append(test[k].rho)
     both = [k for k in range(n_test) if plain_ok[k] and np.isfinite(wres[k]) and wres[k] < tol]
     pi = np.array([plain_it[k] for k in both])
     wi = np.array([wsteps[k] for k in both])
-    return {"workload": f"learned warm start, d=3 N={N} (seed 5): {n_train} training games at N={train_N or N}, "
-                        f"{n_test} held-out",
+    return {"workload": f"learned warm start, d=3 N={N} (seed 5): {n_train} training games solved at N={N}"
+                        + (f" (from their N={coarse_N} solutions)" if coarse_N else "") + f", {n_test} held-out",
             "train_games_converged": int(good.sum()), "train_samples": int(X.shape[0]), "train_steps": train_steps,
+            "train_batch_iterations_coarse": coarse_iters, "train_batch_iterations_fine": fine_iters,
             "data_generation_s": t_data, "training_s": t_train,
             "train_loss_first": float(l0[:10].mean().item()), "train_loss_last": float(l1[-100:].mean().item()),
             "tol": tol, "held_out_converged_both": len(both),
@@ -467,7 +520,10 @@ def run_warm(cg, W, torch, n_train: int = 4096, n_test: int = 64, N: int = 24, t
             "speedup": t_plain / t_warm, "fallbacks": len(fell), "stream_slots": K,
             "stream_time_in_batch_solves_s": t_in_solve, "stream_batch_solve_calls": n_calls,
             "stream_batch_iterations": batch_iters, "stream_total_s": t_warm,
-            "max_rel_V_vs_plain": max(errs) if errs else None}
+            "max_rel_V_vs_plain": max(errs) if errs else None,
+            "median_rel_V_vs_plain": float(np.median(errs)) if errs else None,
+            "p90_rel_V_vs_plain": float(np.quantile(errs, 0.9)) if errs else None,
+            "rho_of_worst": float(err_rho[int(np.argmax(errs))]) if errs else None}
 
 
 def run_eval(cg, W, torch, steps: int, warmup: int, d: int = 4, N: int = 24, npts: int = 1 << 22):
@@ -660,8 +716,10 @@ def main():
                     choices=["c1", "c2", "c3", "batch", "warm", "eval", "sim", "accuracy", "general"])
     ap.add_argument("--no-batch", action="store_true", help="default workload: skip the 256-game batch leg")
     ap.add_argument("--cpu-steps", type=int, default=6, help="oracle iterations timed for the CPU baseline")
+    ap.add_argument("--no-warm", action="store_true", help="default line without the reduced warm-start leg")
     ap.add_argument("--warm-train", type=int, default=4096, help="training games of the warm workload")
-    ap.add_argument("--warm-train-n", type=int, default=12, help="their nodes per dimension (0: same as held-out)")
+    ap.add_argument("--warm-coarse-n", type=int, default=12,
+                    help="coarse grid the training games are first solved on (0: from zero at N=24)")
     ap.add_argument("--warm-steps", type=int, default=40000, help="Adam steps of the warm-start training")
     ap.add_argument("--warm-test", type=int, default=64, help="held-out games of the warm workload")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -700,7 +758,7 @@ def main():
         return
     if args.workload == "warm":
         print(json.dumps(run_warm(cg, W, torch, n_train=args.warm_train, n_test=args.warm_test,
-                                  train_N=args.warm_train_n,
+                                  coarse_N=args.warm_coarse_n,
                                   train_steps=args.warm_steps)), flush=True)
         return
     if args.workload == "c3":
@@ -751,6 +809,17 @@ def main():
             "max_rel_V_vs_fp64_agreeing", "median_rel_V_vs_fp64")}
         out["batch_256_ragged"]["excluded"] = [[e["instance"], e["d"], e["N"], e["top_mode_amplification"]]
                                                for e in b["excluded"]]
+    if not args.no_warm:
+        # the learned warm start at a reduced size (the full study is
+        # --workload warm): 512 training games solved at N = 24, 10 000 Adam
+        # steps, 16 held-out games
+        print("bench: reduced warm-start leg", file=sys.stderr, flush=True)
+        w = run_warm(cg, W, torch, n_train=512, n_test=16, train_steps=10000)
+        out["warm_start_reduced"] = {k: w[k] for k in (
+            "workload", "train_games_converged", "data_generation_s", "training_s", "held_out_converged_both",
+            "plain_fp64_zero_iterations_mean", "warm_iterations_mean", "iteration_ratio",
+            "plain_fp64_one_at_a_time_solves_per_s", "chosen_mixed_batched_warm_solves_per_s", "speedup",
+            "fallbacks", "max_rel_V_vs_plain", "median_rel_V_vs_plain")}
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(g, args.cpu_steps)
