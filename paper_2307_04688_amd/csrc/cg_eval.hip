@@ -205,23 +205,26 @@ __global__ __launch_bounds__(256) void k_eval_mfma(const TE *__restrict__ Bp, co
 // element v).  The contracted index space is (o, i): o runs over mode 0 when
 // d >= 3, i over the other contracted modes (mode 1 when d = 4, then mode d-2
 // padded to N4).  The basis products A_q(i) = T(x_q1) T(x_q,d-2) of a chunk of
-// 32 KSC inner indices are rounded to bf16 once and stay in registers for
+// 32 KSC inner indices (up to 18 K-steps: the whole inner index space of a
+// d = 4, N = 24 series) are rounded to bf16 once and stay in registers for
 // every o; the MFMAs give P_q(o, c) = sum_i A_q(i) C[o, i, c] in f32 and
-// W_q(c) += T_o(x_q0) P_q(o, c), T_o by recurrence in registers.
+// W_q(c) += T_o(x_q0) P_q(o, c), once per (chunk, o).
 //
-// C streams through LDS in slabs of OG outer values x one chunk (FR 1 KB
-// fragments), written by direct global-to-LDS loads into a ring of three
-// buffers, two slabs ahead of the MFMAs, with one barrier per slab.  A wave
-// holds 64 rows (four 16-row blocks) against one 16-column block, so every
-// fragment it reads from LDS feeds four MFMAs; the waves of a row group
-// split the column blocks (for 16 columns: 32 rows per wave).  A block of
-// WPB waves holds 32 WPB points, and every point of it shares each slab the
-// block loads.  The per-row basis tables live in LDS.
+// A wave holds 32 rows (two 16-row blocks) against every column block, so
+// no two waves build the same basis products, and each coefficient fragment
+// it reads from LDS feeds two MFMAs.  C streams through LDS in slabs of OG
+// outer values x KP K-steps of one chunk (at most 12 fragments of 1 KB; a
+// chunk of KSC = 18 steps is three slabs per o), written by direct
+// global-to-LDS loads into a ring of three slabs two ahead of the MFMAs,
+// with one barrier per slab.  The per-row basis tables live in LDS.
 struct Bf16Geo {
     int n_o, n_b, n_l, n_c;  // outer mode, second inner mode (1 if none), mode d-2, last mode
     int K2, CH;              // inner length n_b * N4, chunks of 32 KSC
-    int OG, n_og;            // outer values per slab; slabs per chunk (n_o padded to n_og OG with zeros)
+    int OG, n_og;            // outer values per slab; outer groups (n_o padded to n_og OG with zeros)
 };
+
+// K-steps per slab for a chunk of KSC steps; a chunk is KSC / KP slabs per o.
+__host__ __device__ constexpr int bf16_kp(int ksc) { return ksc <= 6 ? ksc : 6; }
 
 // Packed C: fragment-contiguous, ((((o CH + ch) KSC + ks) NCB + c) 4 + g) 16 + col, 8 bf16 each,
 // for o < n_og OG (zero beyond n_o).
@@ -260,23 +263,24 @@ __device__ __forceinline__ void wait_vmcnt()
     __builtin_amdgcn_s_waitcnt(0x0070 | N);
 }
 
-template <int D, int N4, int NC, int KSC, int WPB>
-__global__ __launch_bounds__(64 * WPB) void k_eval_bf16(const __bf16 *__restrict__ Bp, const double *__restrict__ X,
-                                                        float *__restrict__ out, long long npts, Bf16Geo gg)
+template <int D, int N4, int NC, int KSC>
+__global__ __launch_bounds__(256) void k_eval_bf16(const __bf16 *__restrict__ Bp, const double *__restrict__ X,
+                                                   float *__restrict__ out, long long npts, Bf16Geo gg)
 {
     constexpr int NCB = NC / 16;
-    constexpr int NRG = WPB / NCB;                // row groups; the waves of one split the column blocks
-    constexpr int RB = NCB == 2 ? 4 : 2;          // 16-row blocks per wave
+    constexpr int RB = 2;                         // 16-row blocks per wave
     constexpr int ROWS_W = RB * 16;
-    constexpr int ROWS_B = NRG * ROWS_W;
-    static_assert(ROWS_B == 32 * WPB, "the launcher sizes the grid for 32 points per wave");
+    constexpr int ROWS_B = 4 * ROWS_W;            // 128 points per block of four waves
+    constexpr int KP = bf16_kp(KSC);              // K-steps per slab
+    constexpr int NPART = KSC / KP;               // slabs per (chunk, o)
+    static_assert(NPART * KP == KSC, "a chunk is whole slabs");
     constexpr int LDT = N4;                       // mode-l table stride (floats; 16-byte rows)
     constexpr int LDB = 33;                       // mode-1 table: n_b <= 32 values, zero up to index 32
     constexpr int MAXO = 32;                      // outer values incl. padding (bf16_geo keeps n_og OG <= 32)
     constexpr int FRAG = 512;                     // bf16 per fragment (64 lanes x 16 bytes)
     constexpr int NBUF = 3;
     constexpr int LDW = NC + 1;
-    const int FR = gg.OG * KSC * NCB;             // fragments per slab
+    const int FR = (NPART > 1 ? 1 : gg.OG) * KP * NCB;  // fragments per slab (OG = 1 when NPART > 1)
     const int n_op = gg.n_og * gg.OG;             // outer values incl. padding
     // The tables are arrays of their own, apart from the ring that the
     // direct loads write, so that reading them waits for no load in flight.
@@ -291,7 +295,6 @@ __global__ __launch_bounds__(64 * WPB) void k_eval_bf16(const __bf16 *__restrict
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // scalar: slab addressing stays on the SALU
     const int r16 = lane & 15, g = lane >> 4;
-    const int rg = wave / NCB, cb = wave % NCB;   // row group, column block
     const long long q0 = (long long)blockIdx.x * ROWS_B;
 
     // ---- per-row basis tables by the three-term recurrence in binary32
@@ -339,37 +342,60 @@ __global__ __launch_bounds__(64 * WPB) void k_eval_bf16(const __bf16 *__restrict
     }
     __syncthreads();  // tables visible; no loads in flight past this point
 
-    // slab s = (chunk ch, outer group og), chunk-major; wave w loads
-    // fragments w, w + 4, ... of it, each one wave-wide 1 KB transfer
-    const int nslab = gg.CH * gg.n_og;
-    // (the packed operand holds fewer than 2^22 fragments: 32-bit indices)
+    // slab s = ((chunk ch, outer group og), part p), p fastest; wave w loads
+    // fragments w, w + 4, ... of it, each one wave-wide 1 KB transfer (the
+    // packed operand holds fewer than 2^22 fragments: 32-bit indices).  The
+    // next slab to load is kept as counters (no division in the loop).
+    const int nslab = gg.CH * gg.n_og * NPART;
     const __bf16 *Bl = Bp + lane * 8;
-    auto issue_slab = [&](int s) {
-        const int ch = s / gg.n_og, og = s - ch * gg.n_og;
-        __bf16 *dst = Bs + (s % NBUF) * SLAB;
-        for (int f = wave; f < FR; f += WPB) {
-            const int oo = f / (KSC * NCB), rest = f - oo * (KSC * NCB);
-            const int src = ((og * gg.OG + oo) * gg.CH + ch) * (KSC * NCB) + rest;
-            __builtin_amdgcn_global_load_lds(Bl + src * FRAG,
-                                             (__attribute__((address_space(3))) void *)(dst + f * FRAG), 16, 0, 0);
+    int i_ch = 0, i_og = 0, i_p = 0, i_buf = 0;
+    auto issue_next = [&]() {
+        __bf16 *dst = Bs + i_buf * SLAB;
+        const int base = (((i_og * gg.OG) * gg.CH + i_ch) * KSC + i_p * KP) * NCB;
+        if (NPART > 1) {  // FR = KP NCB fragments, known here: unrolled
+#pragma unroll
+            for (int j = 0; j < (KP * NCB + 3) / 4; ++j) {
+                const int f = wave + 4 * j;
+                if (f < KP * NCB)
+                    __builtin_amdgcn_global_load_lds(
+                        Bl + (base + f) * FRAG, (__attribute__((address_space(3))) void *)(dst + f * FRAG), 16, 0, 0);
+            }
+        } else {
+            for (int f = wave; f < FR; f += 4) {
+                const int oo = f / (KP * NCB), rest = f - oo * (KP * NCB);
+                const int src = base + oo * gg.CH * KSC * NCB + rest;
+                __builtin_amdgcn_global_load_lds(
+                    Bl + src * FRAG, (__attribute__((address_space(3))) void *)(dst + f * FRAG), 16, 0, 0);
+            }
+        }
+        i_buf = i_buf == NBUF - 1 ? 0 : i_buf + 1;
+        if (++i_p == NPART) {
+            i_p = 0;
+            if (++i_og == gg.n_og) {
+                i_og = 0;
+                ++i_ch;
+            }
         }
     };
 
-    f32x4 W[RB];
+    f32x4 W[RB][NCB], P[RB][NCB];
 #pragma unroll
-    for (int rb = 0; rb < RB; ++rb) W[rb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int c = 0; c < NCB; ++c) W[rb][c] = f32x4{0.f, 0.f, 0.f, 0.f};
     bf16x8 a[RB][KSC];
 
-    issue_slab(0);
-    if (nslab > 1) issue_slab(1);
-    const int fw = FR / WPB;  // loads every wave issues per slab (some issue one more)
+    issue_next();
+    if (nslab > 1) issue_next();
+    const int fw = FR / 4;  // loads every wave issues per slab (some issue one more)
+    int c_buf = 0;          // ring buffer of the slab being computed
     for (int ch = 0; ch < gg.CH; ++ch) {
         // basis products A_q(i) of this chunk, rounded to bf16 once; past
         // the inner length the mode-1 factor is zero (table entry, or
         // kb > 0 when there is no mode 1), so the reads need no branch
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
-            const int r = rg * ROWS_W + rb * 16 + r16;
+            const int r = wave * ROWS_W + rb * 16 + r16;
 #pragma unroll
             for (int ks = 0; ks < KSC; ++ks)
 #pragma unroll
@@ -386,45 +412,78 @@ __global__ __launch_bounds__(64 * WPB) void k_eval_bf16(const __bf16 *__restrict
                 }
         }
         for (int og = 0; og < gg.n_og; ++og) {
-            const int s = ch * gg.n_og + og;
-            // slab s complete for this wave (slab s + 1 may stay in flight),
-            // then for every wave; the barrier also retires the reads of
-            // slab s - 1, whose buffer the loads of slab s + 2 reuse
-            if (s + 1 < nslab) {
-                switch (fw) {
-                    case 0: wait_vmcnt<0>(); break;
-                    case 1: wait_vmcnt<1>(); break;
-                    case 2: wait_vmcnt<2>(); break;
-                    case 3: wait_vmcnt<3>(); break;
-                    default: wait_vmcnt<4>(); break;
+#pragma unroll
+            for (int p = 0; p < NPART; ++p) {
+                const int s = (ch * gg.n_og + og) * NPART + p;
+                // slab s complete for this wave (slab s + 1 may stay in
+                // flight), then for every wave; the barrier also retires the
+                // reads of slab s - 1, whose buffer the loads of slab s + 2 reuse
+                if (s + 1 < nslab) {
+                    switch (fw) {
+                        case 0: wait_vmcnt<0>(); break;
+                        case 1: wait_vmcnt<1>(); break;
+                        case 2: wait_vmcnt<2>(); break;
+                        default: wait_vmcnt<3>(); break;
+                    }
+                } else {
+                    wait_vmcnt<0>();
                 }
-            } else {
-                wait_vmcnt<0>();
-            }
-            __builtin_amdgcn_s_barrier();
-            asm volatile("" ::: "memory");
-            if (s + 2 < nslab) issue_slab(s + 2);
+                __builtin_amdgcn_s_barrier();
+                asm volatile("" ::: "memory");
+                if (s + 2 < nslab) issue_next();
 
-            const __bf16 *sb = Bs + (s % NBUF) * SLAB + (cb * 64 + lane) * 8;
-            for (int oo = 0; oo < gg.OG; ++oo) {
-                f32x4 P[RB];
+                const __bf16 *sb = Bs + c_buf * SLAB + lane * 8;
+                c_buf = c_buf == NBUF - 1 ? 0 : c_buf + 1;
+                for (int oo = 0; oo < gg.OG; ++oo) {
+                    // fragment reads run two K-steps ahead of the MFMAs that
+                    // use them (an LDS read outlasts one K-step's four MFMAs)
+                    const __bf16 *so = sb + oo * KP * NCB * FRAG;
+                    bf16x8 b[3][NCB];
 #pragma unroll
-                for (int ks = 0; ks < KSC; ++ks) {
-                    const bf16x8 b = *reinterpret_cast<const bf16x8 *>(sb + ((oo * KSC + ks) * NCB) * FRAG);
+                    for (int kk = 0; kk < 2 && kk < KP; ++kk)
 #pragma unroll
-                    for (int rb = 0; rb < RB; ++rb)  // the first K-step starts from zero
-                        P[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                            a[rb][ks], b, ks == 0 ? f32x4{0.f, 0.f, 0.f, 0.f} : P[rb], 0, 0, 0);
-                }
-                // W += T_o(x_q0) P at the accumulator rows 4g + v
-                const float *to = To + (og * gg.OG + oo) * ROWS_B + rg * ROWS_W + 4 * g;
+                        for (int c = 0; c < NCB; ++c)
+                            b[kk][c] = *reinterpret_cast<const bf16x8 *>(so + (kk * NCB + c) * FRAG);
 #pragma unroll
-                for (int rb = 0; rb < RB; ++rb) {
-                    const float4 t = *reinterpret_cast<const float4 *>(to + rb * 16);
-                    W[rb][0] = fmaf(t.x, P[rb][0], W[rb][0]);
-                    W[rb][1] = fmaf(t.y, P[rb][1], W[rb][1]);
-                    W[rb][2] = fmaf(t.z, P[rb][2], W[rb][2]);
-                    W[rb][3] = fmaf(t.w, P[rb][3], W[rb][3]);
+                    for (int kk = 0; kk < KP; ++kk) {
+                        if (kk + 2 < KP) {
+#pragma unroll
+                            for (int c = 0; c < NCB; ++c)
+                                b[(kk + 2) % 3][c] =
+                                    *reinterpret_cast<const bf16x8 *>(so + ((kk + 2) * NCB + c) * FRAG);
+                        }
+#pragma unroll
+                        for (int c = 0; c < NCB; ++c)
+#pragma unroll
+                            for (int rb = 0; rb < RB; ++rb)  // each o starts from zero
+                                P[rb][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                    a[rb][p * KP + kk], b[kk % 3][c],
+                                    (p == 0 && kk == 0) ? f32x4{0.f, 0.f, 0.f, 0.f} : P[rb][c], 0, 0, 0);
+                    }
+                    // keep that order through scheduling (left alone, the
+                    // scheduler sinks every read next to its MFMAs to save
+                    // registers): the first two steps' reads, then per step
+                    // the reads two ahead and the step's MFMAs
+                    __builtin_amdgcn_sched_group_barrier(0x100, (KP < 2 ? KP : 2) * NCB, 0);
+#pragma unroll
+                    for (int kk = 0; kk < KP; ++kk) {
+                        if (kk + 2 < KP) __builtin_amdgcn_sched_group_barrier(0x100, NCB, 0);
+                        __builtin_amdgcn_sched_group_barrier(0x008, NCB * RB, 0);
+                    }
+                    if (p == NPART - 1) {  // W += T_o(x_q0) P at the accumulator rows 4g + v
+                        const float *to = To + (og * gg.OG + oo) * ROWS_B + wave * ROWS_W + 4 * g;
+#pragma unroll
+                        for (int rb = 0; rb < RB; ++rb) {
+                            const float4 t = *reinterpret_cast<const float4 *>(to + rb * 16);
+#pragma unroll
+                            for (int c = 0; c < NCB; ++c) {
+                                W[rb][c][0] = fmaf(t.x, P[rb][c][0], W[rb][c][0]);
+                                W[rb][c][1] = fmaf(t.y, P[rb][c][1], W[rb][c][1]);
+                                W[rb][c][2] = fmaf(t.z, P[rb][c][2], W[rb][c][2]);
+                                W[rb][c][3] = fmaf(t.w, P[rb][c][3], W[rb][c][3]);
+                            }
+                        }
+                    }
                 }
             }
         }
@@ -436,7 +495,10 @@ __global__ __launch_bounds__(64 * WPB) void k_eval_bf16(const __bf16 *__restrict
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) Wl[(rg * ROWS_W + rb * 16 + 4 * g + v) * LDW + cb * 16 + r16] = W[rb][v];
+        for (int c = 0; c < NCB; ++c)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                Wl[(wave * ROWS_W + rb * 16 + 4 * g + v) * LDW + c * 16 + r16] = W[rb][c][v];
     __syncthreads();
     if (tid < ROWS_B) {
         const long long q = q0 + tid;
@@ -492,33 +554,36 @@ static Bf16Geo bf16_geo(int d, const int *n, int &ksc)
     gg.n_c = n[d - 1];
     gg.K2 = gg.n_b * N4;
     const int steps = (gg.K2 + 31) / 32;
-    // fewest padded steps, counting one step of overhead per chunk
-    const int cand[4] = {6, 4, 2, 1};
+    // K-steps held in registers per chunk: fewest padded steps, counting two
+    // steps of overhead (a W update) per chunk and outer value
+    const int cand[4] = {18, 6, 2, 1};
     int best = 1 << 30;
     ksc = 1;
     for (int c : cand) {
         const int ch = (steps + c - 1) / c;
-        const int cost = ch * c + ch;
-        if (d == 4 && cost < best) {
+        const int cost = ch * (c + 2);
+        if (cost < best) {
             best = cost;
             ksc = c;
         }
     }
-    if (d < 4) ksc = 1;
     gg.CH = (steps + ksc - 1) / ksc;
-    // outer values per slab: at most 12 fragments (three slabs and the
-    // tables leave room for two blocks per CU), at most 32 outer values with
-    // the padding (the kernel's T_o table), fewest padded fragments counting
-    // four of overhead (a barrier) per slab
-    const int f0 = ksc * (n[d - 1] <= 16 ? 1 : 2);
-    best = 1 << 30;
+    // outer values per slab when a chunk is one slab per o: at most 12
+    // fragments (three slabs and the tables leave room for two blocks per
+    // CU), at most 32 outer values with the padding (the kernel's T_o
+    // table), fewest padded fragments counting four of overhead (a barrier)
+    // per slab
+    const int kp = bf16_kp(ksc), f0 = kp * (n[d - 1] <= 16 ? 1 : 2);
     gg.OG = 1;
-    for (int og = 1; og * f0 <= 12; ++og) {
-        if ((gg.n_o + og - 1) / og * og > 32) continue;
-        const int cost = (gg.n_o + og - 1) / og * (og * f0 + 4);
-        if (cost < best) {
-            best = cost;
-            gg.OG = og;
+    if (kp == ksc) {
+        best = 1 << 30;
+        for (int og = 1; og * f0 <= 12; ++og) {
+            if ((gg.n_o + og - 1) / og * og > 32) continue;
+            const int cost = (gg.n_o + og - 1) / og * (og * f0 + 4);
+            if (cost < best) {
+                best = cost;
+                gg.OG = og;
+            }
         }
     }
     gg.n_og = (gg.n_o + gg.OG - 1) / gg.OG;
@@ -565,33 +630,28 @@ static hipError_t launch_eval_dn(const void *Bp, const double *x, TO *out, const
     return hipGetLastError();
 }
 
-// Four waves (128 points) per block: measured at d = 4, N = 24, 2^22
-// points, 4.3 ms against 4.7 ms with eight waves (256 points, which halves
-// the operand traffic per point but fits one block per CU and synchronises
-// eight waves per slab).
 template <int D, int N4, int NC, int KSC>
 static hipError_t launch_bf16_k(const double *coef, void *ws, const double *x, float *out, long long npts,
                                 const Bf16Geo &gg, hipStream_t s)
 {
-    constexpr int WPB = 4;
-    constexpr int ROWS_B = 32 * WPB;
+    constexpr int ROWS_B = 128;
     const long long total = (long long)gg.n_og * gg.OG * gg.CH * KSC * (NC / 16) * 512;
     hipLaunchKernelGGL((k_pack_bf16<KSC, NC / 16>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, coef,
                        (__bf16 *)ws, gg, N4);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     // dynamic LDS: the ring of three slabs, which also stages the W rows
-    const size_t ring = (size_t)3 * gg.OG * KSC * (NC / 16) * 1024;
+    const size_t ring = (size_t)3 * gg.OG * bf16_kp(KSC) * (NC / 16) * 1024;
     const size_t stage = (size_t)ROWS_B * (NC + 1) * sizeof(float);
     const size_t shm = ring > stage ? ring : stage;
     const unsigned blocks = (unsigned)((npts + ROWS_B - 1) / ROWS_B);
     if (shm > 48 * 1024) {
-        e = hipFuncSetAttribute((const void *)k_eval_bf16<D, N4, NC, KSC, WPB>,
+        e = hipFuncSetAttribute((const void *)k_eval_bf16<D, N4, NC, KSC>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((k_eval_bf16<D, N4, NC, KSC, WPB>), dim3(blocks), dim3(64 * WPB), shm, s,
-                       (const __bf16 *)ws, x, out, npts, gg);
+    hipLaunchKernelGGL((k_eval_bf16<D, N4, NC, KSC>), dim3(blocks), dim3(256), shm, s, (const __bf16 *)ws, x, out,
+                       npts, gg);
     return hipGetLastError();
 }
 
@@ -601,21 +661,21 @@ static hipError_t launch_eval_bf16_dn(const double *coef, void *ws, const double
 {
     int ksc;
     const Bf16Geo gg = bf16_geo(D, n, ksc);
-    if constexpr (D < 4) {  // one K-step per chunk (bf16_geo)
+    if constexpr (D < 4) {  // one K-step in all (bf16_geo)
         if (n[D - 1] <= 16) return launch_bf16_k<D, N4, 16, 1>(coef, ws, x, out, npts, gg, s);
         return launch_bf16_k<D, N4, 32, 1>(coef, ws, x, out, npts, gg, s);
     } else {
         if (n[D - 1] <= 16) {
             switch (ksc) {
+                case 18: return launch_bf16_k<D, N4, 16, 18>(coef, ws, x, out, npts, gg, s);
                 case 6: return launch_bf16_k<D, N4, 16, 6>(coef, ws, x, out, npts, gg, s);
-                case 4: return launch_bf16_k<D, N4, 16, 4>(coef, ws, x, out, npts, gg, s);
                 case 2: return launch_bf16_k<D, N4, 16, 2>(coef, ws, x, out, npts, gg, s);
                 default: return launch_bf16_k<D, N4, 16, 1>(coef, ws, x, out, npts, gg, s);
             }
         }
         switch (ksc) {
+            case 18: return launch_bf16_k<D, N4, 32, 18>(coef, ws, x, out, npts, gg, s);
             case 6: return launch_bf16_k<D, N4, 32, 6>(coef, ws, x, out, npts, gg, s);
-            case 4: return launch_bf16_k<D, N4, 32, 4>(coef, ws, x, out, npts, gg, s);
             case 2: return launch_bf16_k<D, N4, 32, 2>(coef, ws, x, out, npts, gg, s);
             default: return launch_bf16_k<D, N4, 32, 1>(coef, ws, x, out, npts, gg, s);
         }
