@@ -158,6 +158,7 @@ def run_batch(cg, W, torch, steps: int, warmup: int, count: int = 256, time_step
     t0 = time.perf_counter()
     rb = B.autotune(2)
     t_tune = time.perf_counter() - t0
+    n_branches = B.branches()
     for _ in range(warmup):
         B.reset()
         B.solve(time_steps)
@@ -214,7 +215,7 @@ def run_batch(cg, W, torch, steps: int, warmup: int, count: int = 256, time_step
             "speedup_vs_fp64_one_at_a_time": (n_agree / t_batch) / (int(ok_s.sum()) / t_single),
             "diverged_batch": int((~ok_b).sum()), "diverged_fp64_one_at_a_time": int((~ok_s).sum()),
             "excluded": excluded,
-            "groups": groups, "tiles_per_group (rows blocks of 16 per wave, outer values per slab)": rb, "autotune_s": t_tune,
+            "groups": groups, "tiles_per_group (rows blocks of 16 per wave, outer values per slab)": rb, "autotune_s": t_tune, "graph_branches": n_branches,
             "max_rel_V_vs_fp64": worst, "max_rms_rel_V_vs_fp64": worst_rms,
             "max_rel_V_vs_fp64_agreeing": max([e for e in errs if e <= 1e-8], default=0.0),
             "err_instances": int((ok_b & ok_s).sum()), "median_rel_V_vs_fp64": float(np.median(errs)),
@@ -804,7 +805,7 @@ def main():
         print("bench: 256-game ragged batch leg", file=sys.stderr, flush=True)
         b = run_batch(cg, W, torch, 1, 1)
         out["batch_256_ragged"] = {k: b[k] for k in (
-            "instances", "time_steps", "ms_per_batch", "solves_per_s", "agreeing_1e-8",
+            "instances", "time_steps", "ms_per_batch", "solves_per_s", "agreeing_1e-8", "graph_branches",
             "fp64_one_at_a_time_solves_per_s", "speedup_vs_fp64_one_at_a_time", "diverged_batch",
             "max_rel_V_vs_fp64_agreeing", "median_rel_V_vs_fp64")}
         out["batch_256_ragged"]["excluded"] = [[e["instance"], e["d"], e["N"], e["top_mode_amplification"]]

@@ -199,8 +199,11 @@ int cg_set_state(cg_game *game, const double *V_dev, const double *U_dev);
  * aligned, device) holds the device tables; work is queued on 'stream'.
  * cg_batch_autotune: for every group, times the contraction's tile shapes
  * (16, 32 or 64 nodes per wave; one or two values of the outer modes per
- * coefficient slab) over 'trial_steps' iterations and keeps the fastest; it
- * resets every game of the batch to V = 0, u = A.  Synchronises.
+ * coefficient slab) over 'trial_steps' iterations and keeps the fastest;
+ * then times 'trial_steps' replays of the captured iteration with 1 to 4
+ * parallel branches and keeps the fastest (more branches only when 2 %
+ * faster); it resets every game of the batch to V = 0, u = A.
+ * Synchronises.
  * cg_batch_solve: like cg_solve for every game at once; steps_done and
  * residuals (host arrays of count entries, nullable) receive each game's
  * iteration count and last residual.  Synchronises.  Returns
@@ -210,7 +213,9 @@ int cg_set_state(cg_game *game, const double *V_dev, const double *U_dev);
  * unaffected (its entries are valid).
  * cg_batch_groups: number of groups and, for arrays that are not NULL (host,
  * CG_MAX_GROUPS entries each), the row blocks of 16 per wave (rb) and the
- * outer values per coefficient slab (ocb) chosen per group. */
+ * outer values per coefficient slab (ocb) chosen per group.
+ * cg_batch_branches: number of parallel branches of the captured iteration
+ * (1 to 4; builds the graph if there is none yet), or a negative error. */
 #define CG_MAX_GROUPS 64
 typedef struct cg_batch cg_batch;
 size_t cg_batch_workspace_bytes(int32_t count);
@@ -219,6 +224,7 @@ int cg_batch_create(cg_game *const *games, int32_t count, void *ws_dev, size_t w
 int cg_batch_autotune(cg_batch *batch, int32_t trial_steps);
 int cg_batch_solve(cg_batch *batch, int32_t max_steps, double tol, int32_t *steps_done, double *residuals);
 int cg_batch_groups(cg_batch *batch, int32_t *rb, int32_t *ocb);
+int cg_batch_branches(cg_batch *batch);
 int cg_batch_destroy(cg_batch *batch);
 
 /* Learned warm start (an addition to the method: Section 2.2 leaves the

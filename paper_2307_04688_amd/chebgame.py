@@ -88,6 +88,7 @@ def lib() -> C.CDLL:
     L.cg_batch_autotune.argtypes = [vp, C.c_int32]
     L.cg_batch_solve.argtypes = [vp, C.c_int32, C.c_double, ip, dp]
     L.cg_batch_groups.argtypes = [vp, ip, ip]
+    L.cg_batch_branches.argtypes = [vp]
     L.cg_batch_destroy.argtypes = [vp]
     fp = C.POINTER(C.c_float)
     L.cg_mlp_param_count.restype = C.c_int64
@@ -288,6 +289,10 @@ class ChebBatch:
         ocb = (C.c_int32 * 64)()
         n = _check(lib().cg_batch_groups(self.handle, rb, ocb))
         return list(zip(rb[:n], ocb[:n]))
+
+    def branches(self) -> int:
+        """Parallel branches of the captured iteration."""
+        return _check(lib().cg_batch_branches(self.handle))
 
     def solve(self, max_steps: int, tol: float = 0.0):
         """Returns (status, steps_done[count], last residual[count]).  A game

@@ -109,6 +109,7 @@ struct cg_batch {
     hipGraphExec_t exec;
     bool have_graph;
     int branches;              // parallel branches of the captured iteration
+    int max_branches;          // at most this many (the autotuner's choice; kBranches before)
     std::vector<int> branch_of;  // per group
     std::vector<StatusCopy> host_status;
     ~cg_batch()
@@ -162,7 +163,7 @@ double group_cost(const Group &G)
 void assign_branches(cg_batch *B)
 {
     const int ng = (int)B->groups.size();
-    B->branches = std::min(kBranches, ng);
+    B->branches = std::min(B->max_branches, ng);
     B->branch_of.assign(ng, 0);
     std::vector<double> load(B->branches, 0.0);
     for (int g = 0; g < ng; ++g) {  // groups are sorted largest first
@@ -268,6 +269,7 @@ int cg_batch_create(cg_game *const *games, int32_t count, void *ws_dev, size_t w
     }
     B->have_graph = false;
     B->branches = 1;
+    B->max_branches = kBranches;
     B->host_status.resize(count);
     // group by (d, N, control-fit path, precision)
     for (int i = 0; i < count; ++i) {
@@ -381,6 +383,33 @@ int cg_batch_autotune(cg_batch *B, int32_t trial_steps)
         G.ocb = best_ocb;
         if (rc != CG_OK) break;
     }
+    // then the parallel branches of the captured iteration: trial_steps
+    // replays of the graph with 1 .. kBranches branches; more branches are
+    // kept only when at least 2 % faster
+    const int nb_max = std::min(kBranches, (int)B->groups.size());
+    float best_t = 1e30f;
+    int best_nb = nb_max;
+    for (int nb = 1; nb <= nb_max && rc == CG_OK; ++nb) {
+        B->max_branches = nb;
+        rc = build_graph(B);
+        if (rc != CG_OK) break;
+        hipError_t e = hipGraphLaunch(B->exec, B->stream);  // warm-up
+        if (e == hipSuccess) e = hipEventRecord(e0, B->stream);
+        for (int s = 0; s < trial_steps && e == hipSuccess; ++s) e = hipGraphLaunch(B->exec, B->stream);
+        if (e == hipSuccess) e = hipEventRecord(e1, B->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) {
+            rc = hip_err(e, "autotune branches");
+            break;
+        }
+        if (ms < 0.98f * best_t) {
+            best_t = ms;
+            best_nb = nb;
+        }
+    }
+    B->max_branches = best_nb;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc != CG_OK) return rc;
@@ -446,6 +475,16 @@ int cg_batch_groups(cg_batch *B, int32_t *rb, int32_t *ocb)
         if (ocb) ocb[i] = B->groups[i].ocb;
     }
     return (int)B->groups.size();
+}
+
+int cg_batch_branches(cg_batch *B)
+{
+    if (!B) return set_error(CG_EINVAL, "batch is NULL");
+    if (!B->have_graph) {
+        int rc = build_graph(B);
+        if (rc != CG_OK) return rc;
+    }
+    return B->branches;
 }
 
 int cg_batch_destroy(cg_batch *B)

@@ -154,6 +154,7 @@ def test_batch_autotune_and_reset(cg):
     B = cg.ChebBatch(handles)
     tiles = B.autotune(2)
     assert len(tiles) == len(B.groups()) and all(r in (1, 2, 4) and o in (1, 2) for r, o in tiles)
+    assert 1 <= B.branches() <= min(4, len(tiles))
     rc, steps, _ = B.solve(12)
     assert np.all(steps == 12)
     for g, h in zip(games, handles):
