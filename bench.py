@@ -10,8 +10,10 @@ argmax, residual).  Prints one JSON line.
   python bench.py [--steps K] [--warmup W] [--precision fp64|fp32corr]
 
 The reported value is the mixed path (binary32 MFMA remainder with FP64
-correction); the FP64 path is timed beside it.  Other workloads print their
-own JSON line: --workload c3 (d=4, N=24 solve), batch (256 ragged games),
+correction); the FP64 path is timed beside it, and the line also carries a
+256-game ragged batch leg and a reduced learned-warm-start leg (--no-batch,
+--no-warm leave them out).  Other workloads print their own JSON line:
+--workload c1 (d=2, N=16 iteration latency), c3 (d=4, N=24 solve), batch (256 ragged games),
 warm (learned warm start), eval (standalone evaluation), sim (equilibrium
 paths), accuracy (error against the continuous-time equilibrium), general
 (the general form: non-separable game, anisotropic grids).
