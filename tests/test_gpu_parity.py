@@ -304,6 +304,30 @@ def test_c2_workload_against_oracle_reference(cg):
     assert clip_seen  # the bound binds within the run
 
 
+def test_c2_workload_against_long_double_oracle(cg):
+    """The same 200 FP64 steps against the oracle's long double run (64-bit
+    significand; tests/golden/make_c2_reference.py --ext) at its 23
+    snapshots: the GPU's binary64 rounding stays below the FP64 bar against
+    a reference whose own rounding is 2^-11 of binary64's."""
+    path = os.path.join(GOLD, "c2_oracle_reference_ext.json")
+    ref = json.load(open(path))
+    g = W.config_game("C2")
+    say("C2 200 steps vs long double reference")
+    G = _gpu_game(cg, g)
+    pl, nd = np.array(ref["players"]), np.array(ref["nodes"])
+    done = 0
+    for s in sorted(int(k) for k in ref["snapshots"]):
+        G.step(s - done)
+        done = s
+        V, U, _ = G.get_state()
+        V, U = V.cpu().numpy(), U.cpu().numpy()
+        snap = ref["snapshots"][str(s)]
+        ev = np.max(np.abs(V[pl, nd] - np.array(snap["V"]))) / ref["vmax"][s - 1]
+        eu = np.max(np.abs(U[pl, nd] - np.array(snap["U"]))) / g.u_max
+        say(f"  step {s}: rel V {ev:.2e} u {eu:.2e}")
+        assert ev <= 1e-12 and eu <= 1e-10, s
+
+
 def test_solve_tolerance_matches_oracle(cg, orc):
     g = W.make_game(2, 6, seed=1, nominal=True, p_max=0.5, h=0.05)
     _, _, res = orc.solve(g, 300)

@@ -5,6 +5,7 @@ smaller input, so that stale scratch contents of the first call would show in
 the second; the first call uses the largest size of the compiled set (d = 4,
 N = 32), which fills the static array exactly in FP64.
 """
+import gc
 import sys
 
 import numpy as np
@@ -48,12 +49,19 @@ def test_noalloc_matches_workspace_entry(cg, precision):
     odt = torch.float64 if precision == cg.FP64 else torch.float32
     out1 = torch.empty(3000, dtype=odt, device="cuda")
     out2 = torch.empty(517, dtype=odt, device="cuda")
-    torch.cuda.synchronize()
-    before = torch.cuda.memory_allocated()
-    cg.chebyshev_eval_noalloc(*big, precision=precision, out=out1)
-    cg.chebyshev_eval_noalloc(*small, precision=precision, out=out2)
-    torch.cuda.synchronize()
-    assert torch.cuda.memory_allocated() == before
+    # tensors of earlier tests that the garbage collector frees in between
+    # would lower the count: collect first and hold the collector off
+    gc.collect()
+    gc.disable()
+    try:
+        torch.cuda.synchronize()
+        before = torch.cuda.memory_allocated()
+        cg.chebyshev_eval_noalloc(*big, precision=precision, out=out1)
+        cg.chebyshev_eval_noalloc(*small, precision=precision, out=out2)
+        torch.cuda.synchronize()
+        assert torch.cuda.memory_allocated() == before
+    finally:
+        gc.enable()
     ref1 = cg.chebyshev_eval(*big, precision=precision)
     ref2 = cg.chebyshev_eval(*small, precision=precision)
     torch.cuda.synchronize()
