@@ -54,7 +54,7 @@ int check_device()
 }
 
 struct Layout {
-    size_t gc, st, tab, V, U, coef, tmp, Bp, W, Bp32, E, blk, total;
+    size_t gc, st, tab, V, U, coef, tmp, Bp, W, Bp32, Bs16, E, blk, total;
 };
 
 int validate(const cg_game_desc *g, int precision)
@@ -116,9 +116,13 @@ Layout layout(const cg_game_desc *g, int precision)
     L.Bp = o; o = align256(o + sizeof(double) * (size_t)g->d * K * NC);
     L.W = o; o = align256(o + sizeof(double) * (size_t)g->d * NN * NC);
     L.blk = o; o = align256(o + sizeof(double) * (size_t)g->d * ((NN + 63) / 64));
-    L.Bp32 = L.E = 0;
+    L.Bp32 = L.Bs16 = L.E = 0;
     if (precision == CG_FP32_CORR) {
         L.Bp32 = o; o = align256(o + sizeof(float) * (size_t)g->d * K * NC);
+        if (corr3_split16(g->d, N4)) {
+            L.Bs16 = o;
+            o = align256(o + sizeof(unsigned short) * (size_t)g->d * split16_player(g->n_nodes, NC));
+        }
         // Taylor tensors [d][d][N^(d-1)][NC] (FP64), then the d = 3 nodal tensors
         // [d][d-1][N^(d-2)][64 lanes][corr3_chunk] (binary32, fragment order)
         L.E = o; o = align256(o + sizeof(double) * (size_t)g->d * g->d * (NN / g->n_nodes) * NC +
@@ -216,6 +220,7 @@ Inst inst_offsets(const InstPtrs &p, const void *table_dev)
     e.Bp = off(p.Bp);
     e.W = off(p.W);
     e.Bp32 = off(p.Bp32);
+    e.Bs16 = off(p.Bs16);
     e.E = off(p.E);
     e.blk = off(p.blk);
     return e;
@@ -415,6 +420,7 @@ int cg_init_game(const cg_game_desc *g, int precision, void *ws_dev, size_t ws_b
     b.Bp = (double *)(G->ws + L.Bp);
     b.W = (double *)(G->ws + L.W);
     b.Bp32 = precision == CG_FP32_CORR ? (float *)(G->ws + L.Bp32) : nullptr;
+    b.Bs16 = L.Bs16 ? (unsigned short *)(G->ws + L.Bs16) : nullptr;
     b.E = precision == CG_FP32_CORR ? (double *)(G->ws + L.E) : nullptr;
     b.blk = (double *)(G->ws + L.blk);
     b.precision = precision;
@@ -432,6 +438,7 @@ int cg_init_game(const cg_game_desc *g, int precision, void *ws_dev, size_t ws_b
     hi.Bp = b.Bp;
     hi.W = b.W;
     hi.Bp32 = b.Bp32;
+    hi.Bs16 = b.Bs16;
     hi.E = b.E;
     hi.blk = b.blk;
     G->prof = false;
@@ -454,6 +461,11 @@ int cg_init_game(const cg_game_desc *g, int precision, void *ws_dev, size_t ws_b
         // binary32 operand: zero it through a double view (its size is a multiple of 2 floats)
         hipLaunchKernelGGL(k_zero, dim3(256), dim3(256), 0, G->stream, (double *)b.Bp32,
                            (long long)hc.d * hc.K * hc.NC / 2);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess && b.Bs16) {  // padding pieces stay zero (4 bf16 per double)
+        hipLaunchKernelGGL(k_zero, dim3(256), dim3(256), 0, G->stream, (double *)b.Bs16,
+                           (long long)hc.d * split16_player(hc.N, hc.NC) / 4);
         e = hipGetLastError();
     }
     if (e == hipSuccess && b.E) {

@@ -40,6 +40,15 @@ struct GameConst {
 // in MFMA fragment order (lane-contiguous, padded to whole float4 loads).
 __host__ __device__ constexpr int corr3_chunk(int N4, int NC) { return ((N4 / 4) * (NC / 16) + 3) & ~3; }
 
+// d = 3 mixed contraction in split bfloat16 form: every binary32 coefficient
+// of the packed operand is stored as three bfloat16 pieces (exact sum), and
+// the main product runs on bf16 MFMA with K = 32 per step.  Used from N4 = 20
+// on; below, the padding of K to 32 costs more than the bf16 rate gains.
+__host__ __device__ constexpr bool corr3_split16(int d, int N4) { return d == 3 && N4 >= 20; }
+// bf16 elements of the split operand of one player: N outer values x 3
+// pieces x (NC / 16) column blocks x 64 lanes x 8
+__host__ __device__ constexpr long long split16_player(int N, int NC) { return (long long)N * 3 * (NC / 16) * 512; }
+
 // Per-game device status words.
 struct GameStatus {
     double last_res;                 // residual of the last finished step
@@ -70,6 +79,7 @@ struct InstPtrs {
     double *Bp;              // packed operand (FP64)
     double *W;               // line coefficients
     float *Bp32;             // packed operand (binary32, FP32_CORR)
+    unsigned short *Bs16;    // packed operand split in bfloat16 pieces (FP32_CORR, corr3_split16)
     double *E;               // FP32_CORR Taylor tensors
     double *blk;             // per-block residual maxima of the line kernel
 };
@@ -81,7 +91,7 @@ struct InstPtrs {
 // kernel argument) plus an offset are known to the compiler to be global
 // memory, so loads and stores through them are global (not flat) accesses.
 struct Inst {
-    long long gc, st, V, U, coef, tmp, Bp, W, Bp32, E, blk;
+    long long gc, st, V, U, coef, tmp, Bp, W, Bp32, Bs16, E, blk;
 };
 Inst inst_offsets(const InstPtrs &p, const void *table_dev);
 
@@ -90,6 +100,7 @@ struct InstView {
     GameStatus *st;
     double *V, *U, *coef, *tmp, *Bp, *W;
     float *Bp32;
+    unsigned short *Bs16;
     double *E, *blk;
 };
 __device__ __forceinline__ InstView inst_view(const Inst *tab, int k)
@@ -106,6 +117,7 @@ __device__ __forceinline__ InstView inst_view(const Inst *tab, int k)
     v.Bp = (double *)(b + e.Bp);
     v.W = (double *)(b + e.W);
     v.Bp32 = (float *)(b + e.Bp32);
+    v.Bs16 = (unsigned short *)(b + e.Bs16);
     v.E = (double *)(b + e.E);
     v.blk = (double *)(b + e.blk);
     return v;
@@ -121,6 +133,7 @@ struct StepBuffers {
     double *Bp;              // d * K * NC packed operand (FP64)
     double *W;               // d * NN * NC line coefficients (contraction output)
     float *Bp32;             // d * K * NC packed operand in binary32 (FP32_CORR)
+    unsigned short *Bs16;    // d * split16_player bf16 pieces of it (FP32_CORR, corr3_split16)
     double *E;               // FP32_CORR: [d][d][N^(d-1)][NC] value / first-order tensors
     double *blk;             // per-block residual maxima of the line kernel (d ceil(N^d / 64))
     int precision;

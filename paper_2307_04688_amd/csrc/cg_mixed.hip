@@ -486,11 +486,21 @@ __global__ __launch_bounds__(256) void k_contract_corr(const Inst *__restrict__ 
 // element (the outer factor D_o of a row comes from an LDS table), against
 // three for the general recursion above.
 //
+// Split form (SPLIT, corr3_split16): the main GEMM runs in two levels on
+// v_mfma_f32_16x16x32_bf16.  Per outer value k_o, P[r][k_i] = sum_kn D_n[r][kn]
+// C[k_o][kn][k_i] with both operands as three bfloat16 pieces (D_n split once
+// per row, C split by the transform) and the six piece products of leading
+// order (hi hi, hi mid, mid hi, hi lo, mid mid, lo hi; the three dropped
+// ones are below 2^-24 of the product), accumulated in binary32; then
+// acc += D_o[r][k_o] P on the VALU.  The K index of the MFMA runs over
+// kn = 4 e + g (lane group g, element e), the layout of the stride-4 basis
+// recurrences, padded to 32 with zeros.
+//
 // Rows: the nodes of player i ordered by line, r = (jo N + jn) N + ji, so the
 // 16 rows of an MFMA block share (jo, jn) when N is a multiple of 16; a block
 // that straddles lines runs the E2 terms once per line, the A rows of the
 // other lines masked to zero.  binary32 partial sums enter FP64 every FOLD
-// slabs (FOLD OCB N4 K-rows).
+// slabs (FOLD OCB N4 K-rows), in the split form once after the last slab.
 // Slab sb (OCB outer values) of the packed binary32 coefficients into
 // registers: float4 element e4 = tid + NTHR q of the slab.  Outer values past
 // the last one (slabs padded to whole groups) read the last one's
@@ -507,6 +517,15 @@ __device__ __forceinline__ void corr3_load(f32x4 (&pf)[PF], const f32x4 *__restr
         pf[q] = Bg[(long long)oc * OC_E4 + e4 % OC_E4];
     }
 }
+template <int PF, int SLAB_E4, int NTHR>
+__device__ __forceinline__ void corr3_store_flat(const f32x4 (&pf)[PF], float *buf, int tid)
+{
+#pragma unroll
+    for (int q = 0; q < PF; ++q) {
+        const int e4 = tid + q * NTHR;
+        if (SLAB_E4 % NTHR == 0 || e4 < SLAB_E4) reinterpret_cast<f32x4 *>(buf)[e4] = pf[q];
+    }
+}
 template <int PF, int SLAB_E4, int NC, int LDB, int NTHR>
 __device__ __forceinline__ void corr3_store(const f32x4 (&pf)[PF], float *buf, int tid)
 {
@@ -520,8 +539,11 @@ __device__ __forceinline__ void corr3_store(const f32x4 (&pf)[PF], float *buf, i
     }
 }
 
-template <int N4, int NC, int RB, int OCB, int FOLD, int WPB, int NX>
-__global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(RB == 1 ? 3 : 1))) void k_contract_corr3(
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+template <int N4, int NC, int RB, int OCB, int FOLD, int WPB, int NX, bool SPLIT>
+__global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(RB == 1 ? 3 : (SPLIT && RB == 2 ? 2 : 1))))
+void k_contract_corr3(
     const Inst *__restrict__ tab, int bpi, int blocks_per_player)
 {
     // NX = N when N is known at compile time (N = N4, every shape of the
@@ -540,13 +562,16 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(RB == 
     constexpr int ROWS_B = WPB * ROWS_W;         // WPB waves share every coefficient slab
     constexpr int NTHR = 64 * WPB;
     constexpr int LDB = NC == 32 ? 48 : 16;      // slab rows (floats): kq groups on disjoint banks
-    constexpr int SLAB = OCB * N4 * LDB;         // OCB outer values per slab
-    constexpr int OC_E4 = N4 * NC / 4;           // float4 elements per outer value
+    // float4 elements per outer value: binary32 N4 x NC, or (split form) 3
+    // pieces x NCB fragments of 64 lanes x 16 bytes, copied as stored
+    constexpr int OC_E4 = SPLIT ? 3 * NCB * 64 : N4 * NC / 4;
+    constexpr int SLAB = SPLIT ? OCB * OC_E4 * 4 : OCB * N4 * LDB;  // floats; OCB outer values per slab
     constexpr int SLAB_E4 = OCB * OC_E4;
     constexpr int PF = (SLAB_E4 + NTHR - 1) / NTHR;
-    constexpr int LDO = N4 + 1;                  // row stride of the D_o table
-    __shared__ float lds[2 * SLAB];
-    __shared__ float dO[ROWS_B * LDO];
+    constexpr int LDO = N4 + 1;                  // row stride of the D_o table [row][k_o]
+    constexpr int LDT = ROWS_B;                  // split form: the table transposed, [k_o][row]
+    __shared__ __attribute__((aligned(16))) float lds[2 * SLAB];
+    __shared__ __attribute__((aligned(16))) float dO[SPLIT ? N4 * LDT : ROWS_B * LDO];
     __shared__ double dls[ROWS_B * 2];           // Delta_o, Delta_n of every row, for the epilogue
 
     if (st->converged) return;
@@ -573,7 +598,8 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(RB == 
     // ---- the first coefficient slab and the nodal tensors of each row block's
     //      first line (lane-contiguous float4 loads), issued first so that
     //      their latency overlaps the per-row work ----
-    const f32x4 *Bg = reinterpret_cast<const f32x4 *>(I.Bp32 + (long long)player * gc->K * NC);
+    const f32x4 *Bg = SPLIT ? reinterpret_cast<const f32x4 *>(I.Bs16 + player * split16_player(N, NC))
+                            : reinterpret_cast<const f32x4 *>(I.Bp32 + (long long)player * gc->K * NC);
     const int n_outer = N;
     f32x4 pf0[PF];
     corr3_load<PF, SLAB_E4, OC_E4, OCB, NTHR>(pf0, Bg, 0, n_outer, tid);
@@ -628,7 +654,11 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(RB == 
             mn.advance4();
             mo.get(T, Tb, P, R1);
             R1o[rb][t] = (float)R1;
-            dO[rl * LDO + 4 * t + kq] = 4 * t + kq < N ? (float)(T - Tb) : 0.f;  // outer values past N: zero rows
+            const float dov = 4 * t + kq < N ? (float)(T - Tb) : 0.f;  // outer values past N: zero rows
+            if constexpr (SPLIT)
+                dO[(4 * t + kq) * LDT + rl] = dov;
+            else
+                dO[rl * LDO + 4 * t + kq] = dov;
             mo.advance4();
         }
     }
@@ -650,7 +680,10 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(RB == 
     static_assert(OCB * FOLD == 4 && (FOLD % 2 == 0), "four outer values per group, even FOLD");
     const int n_groups = (n_outer + OCB * FOLD - 1) / (OCB * FOLD);
     const int n_slabs = n_groups * FOLD;
-    corr3_store<PF, SLAB_E4, NC, LDB, NTHR>(pf0, lds, tid);
+    if constexpr (SPLIT)
+        corr3_store_flat<PF, SLAB_E4, NTHR>(pf0, lds, tid);
+    else
+        corr3_store<PF, SLAB_E4, NC, LDB, NTHR>(pf0, lds, tid);
     __syncthreads();  // also publishes the D_o table
 
     // ---- one-mode remainder terms against the nodal tensors of each line
@@ -692,7 +725,28 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(RB == 
         }
     }
 
-    for (int g = 0; g < n_groups; ++g) {
+    // split form: D_n of each row as three bfloat16 pieces, element e = k / 4
+    // of lane group kq (k = 4 e + kq), zero past N4
+    bf16x8 a16[RB][3];
+    if constexpr (SPLIT) {
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                float r = e < NT ? Dn[rb][e] : 0.f;
+#pragma unroll
+                for (int p = 0; p < 3; ++p) {
+                    const __bf16 h = (__bf16)r;
+                    a16[rb][p][e] = h;
+                    r -= (float)h;
+                }
+            }
+    }
+
+    // one group of four outer values; the split form keeps the group loop
+    // rolled (a known trip count would otherwise unroll it whole and hoist
+    // every slab load)
+    auto run_group = [&](const int g) __attribute__((always_inline)) {
 #pragma unroll
         for (int q = 0; q < FOLD; ++q) {
             const int sb = g * FOLD + q;
@@ -700,6 +754,41 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(RB == 
             f32x4 pf[PF];
             // (the last slab loads a valid, unused slab: pf stays unconditionally defined)
             corr3_load<PF, SLAB_E4, OC_E4, OCB, NTHR>(pf, Bg, more ? sb + 1 : sb, n_outer, tid);
+            if constexpr (SPLIT) {
+#pragma unroll
+                for (int ocl = 0; ocl < OCB; ++ocl) {
+                    const int oc = sb * OCB + ocl;
+                    const f32x4 *fb = reinterpret_cast<const f32x4 *>(lds + (q & 1) * SLAB) + ocl * OC_E4 + lane;
+                    bf16x8 b16[3][NCB];
+#pragma unroll
+                    for (int p = 0; p < 3; ++p)
+#pragma unroll
+                        for (int c = 0; c < NCB; ++c) b16[p][c] = __builtin_bit_cast(bf16x8, fb[(p * NCB + c) * 64]);
+                    f32x4 fo4[RB];  // D_o of output rows 4 kq + v
+#pragma unroll
+                    for (int rb = 0; rb < RB; ++rb)
+                        fo4[rb] = *reinterpret_cast<const f32x4 *>(dO + oc * LDT + wave * ROWS_W + rb * 16 + 4 * kq);
+                    __builtin_amdgcn_sched_barrier(0);
+                    // piece products (A piece, B piece), smallest first
+                    constexpr int PA[6] = {2, 1, 0, 1, 0, 0}, PB[6] = {0, 1, 2, 0, 1, 0};
+                    f32x4 P[RB][NCB];
+#pragma unroll
+                    for (int pp = 0; pp < 6; ++pp)
+#pragma unroll
+                        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                            for (int c = 0; c < NCB; ++c)
+                                P[rb][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                    a16[rb][PA[pp]], b16[PB[pp]][c],
+                                    pp == 0 ? f32x4{0.f, 0.f, 0.f, 0.f} : P[rb][c], 0, 0, 0);
+#pragma unroll
+                    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                        for (int c = 0; c < NCB; ++c)
+#pragma unroll
+                            for (int v = 0; v < 4; ++v) acc[rb][c][v] = fmaf(fo4[rb][v], P[rb][c][v], acc[rb][c][v]);
+                }
+            } else {
 #pragma unroll
             for (int ocl = 0; ocl < OCB; ++ocl) {
                 const int oc = sb * OCB + ocl;
@@ -727,15 +816,41 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(RB == 
                     }
                 }
             }
-            if (more) corr3_store<PF, SLAB_E4, NC, LDB, NTHR>(pf, lds + ((q + 1) & 1) * SLAB, tid);
+            }
+            if (more) {
+                if constexpr (SPLIT)
+                    corr3_store_flat<PF, SLAB_E4, NTHR>(pf, lds + ((q + 1) & 1) * SLAB, tid);
+                else
+                    corr3_store<PF, SLAB_E4, NC, LDB, NTHR>(pf, lds + ((q + 1) & 1) * SLAB, tid);
+            }
             __syncthreads();
         }
+        if constexpr (!SPLIT) {
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                for (int c = 0; c < NCB; ++c)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) acc64[rb][c][v] += (double)acc[rb][c][v];
+        }
+    };
+    if constexpr (SPLIT) {
+        // the split form sums every outer value in binary32 (the 6 x 32 piece
+        // products of one outer value already are) and enters FP64 once
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int c = 0; c < NCB; ++c) acc[rb][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 1
+        for (int g = 0; g < n_groups; ++g) run_group(g);
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
             for (int c = 0; c < NCB; ++c)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) acc64[rb][c][v] += (double)acc[rb][c][v];
+    } else {
+        for (int g = 0; g < n_groups; ++g) run_group(g);
     }
 
     // ---- epilogue: element v of lane c + 16 kq is row 4 kq + v (f32 layout);
@@ -790,14 +905,15 @@ static hipError_t launch_corr3_nrx(const GameConst &hc, const StepBuffers &b, hi
 {
     constexpr int NC = N4 <= 16 ? 16 : 32;
     constexpr int W = kCorr3Waves;
+    constexpr bool SPLIT = corr3_split16(3, N4);
     const int NN = (int)hc.NN;
     const int bpp = (NN + W * RB * 16 - 1) / (W * RB * 16);
     const int bpi = bpp * 3;
     if (b.ocb == 2)
-        hipLaunchKernelGGL((k_contract_corr3<N4, NC, RB, 2, 2, W, NX>), dim3((unsigned)(bpi * b.count)),
+        hipLaunchKernelGGL((k_contract_corr3<N4, NC, RB, 2, 2, W, NX, SPLIT>), dim3((unsigned)(bpi * b.count)),
                            dim3(64 * W), 0, s, b.tab, bpi, bpp);
     else
-        hipLaunchKernelGGL((k_contract_corr3<N4, NC, RB, 1, 4, W, NX>), dim3((unsigned)(bpi * b.count)),
+        hipLaunchKernelGGL((k_contract_corr3<N4, NC, RB, 1, 4, W, NX, SPLIT>), dim3((unsigned)(bpi * b.count)),
                            dim3(64 * W), 0, s, b.tab, bpi, bpp);
     return hipGetLastError();
 }

@@ -32,6 +32,29 @@ __device__ __forceinline__ long long packed_index(const GameConst *__restrict__ 
     return ((long long)i * gc->K + (long long)kout * gc->N4 + kl) * gc->NC + col;
 }
 
+// Split form of the d = 3 packed operand (corr3_split16): element
+// (k_o, k_n, k_i) of player i, rounded to binary32, as three bfloat16 pieces
+// whose sum is that binary32 value exactly (each piece takes the leading bits
+// of what the previous ones left; 3 x 8 significand bits cover 24).  Order:
+// MFMA fragments of v_mfma_f32_16x16x32_bf16 with k_n as the K index, per
+// (player, k_o, piece, column block k_i / 16) 64 lanes x 8 elements, element
+// (k_n, k_i) in lane (k_n mod 4) 16 + k_i mod 16 at position k_n / 4.
+__device__ __forceinline__ void store_split16(unsigned short *__restrict__ Bs, const GameConst *__restrict__ gc, int i,
+                                              const int *dig, double v)
+{
+    const int ko = dig[i == 0 ? 1 : 0], kn = dig[i == 2 ? 1 : 2], ki = dig[i];
+    const int NCB = gc->NC / 16;
+    const long long frag0 = ((long long)i * gc->N + ko) * 3 * NCB + (ki >> 4);
+    const int slot = ((kn & 3) * 16 + (ki & 15)) * 8 + (kn >> 2);
+    float r = (float)v;
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+        const __bf16 h = (__bf16)r;
+        Bs[(frag0 + (long long)p * NCB) * 512 + slot] = __builtin_bit_cast(unsigned short, h);
+        r -= (float)h;
+    }
+}
+
 // Body of the first transform pass for block 'bid' (sm: 3 kMaxN (kMaxN + 1)
 // doubles of LDS), shared by k_tf_fast and the fused pass + Taylor kernel.
 template <int NP>

@@ -99,6 +99,7 @@ __global__ __launch_bounds__(256) void k_tf_outer(const Inst *__restrict__ tab, 
     const double *__restrict__ in = I.tmp;
     double *Bp = I.Bp;
     float *Bp32 = mixed ? I.Bp32 : nullptr;
+    unsigned short *Bs16 = mixed && corr3_split16(gc->d, gc->N4) ? I.Bs16 : nullptr;
     extern __shared__ double sh[];
     if (st->converged) return;
     const int N = gc->N, d = gc->d, NN2 = N * N;
@@ -124,6 +125,7 @@ __global__ __launch_bounds__(256) void k_tf_outer(const Inst *__restrict__ tab, 
             double acc = 0.0;
             for (int k = 0; k < N; ++k) acc = fma(Dm[l * LD + k], X[k * Q + qq], acc);
             int dig[kMaxD] = {l, q / N, q % N, 0};
+            if (Bs16) { store_split16(Bs16, gc, i, dig, acc); continue; }
             const long long o = packed_index(gc, i, dig);
             if (Bp32) Bp32[o] = (float)acc; else Bp[o] = acc;
         }
@@ -160,6 +162,7 @@ __global__ __launch_bounds__(256) void k_tf_mode0(const Inst *__restrict__ tab, 
     const double *__restrict__ in = I.tmp;
     double *Bp = I.Bp;
     float *Bp32 = mixed ? I.Bp32 : nullptr;
+    unsigned short *Bs16 = mixed && corr3_split16(gc->d, gc->N4) ? I.Bs16 : nullptr;
     constexpr int LD = kMaxN + 1;
     __shared__ double Dm[kMaxN * LD];
     __shared__ double X[kMaxN * LD];
@@ -185,6 +188,7 @@ __global__ __launch_bounds__(256) void k_tf_mode0(const Inst *__restrict__ tab, 
             const int l = ti * 16 + kq + 4 * v, q = q0 + tj * 16 + r16;
             if (l >= N || q >= NN2) continue;
             int dig[kMaxD] = {l, q / N, q % N, 0};
+            if (Bs16) { store_split16(Bs16, gc, i, dig, acc[v]); continue; }
             const long long o = packed_index(gc, i, dig);
             if (Bp32) Bp32[o] = (float)acc[v]; else Bp[o] = acc[v];
         }

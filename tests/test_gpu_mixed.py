@@ -73,13 +73,16 @@ def test_mixed_every_step_small_games(cg, orc, d, N, steps):
     say(f"  d={d} N={N}: worst rel V over {steps} steps {worst:.2e}")
 
 
-@pytest.mark.parametrize("d,N", [(3, 32), (3, 24), (3, 20), (3, 13), (4, 24), (4, 21), (2, 32)])
+@pytest.mark.parametrize("d,N", [(3, 32), (3, 24), (3, 20), (3, 13), (3, 30), (3, 27), (3, 28), (3, 18),
+                                 (4, 24), (4, 21), (2, 32)])
 def test_mixed_one_step_from_smooth_state(cg, orc, d, N):
     """One mixed step from a seeded smooth state (a value function's shape:
     quadratic plus sines) against the oracle's step (sampled (player, node)
     pairs above 5000 nodes): V within 1e-9 of max|V|, u within 1e-8 u_max.  Covers the contraction instantiations of the
     benchmark shapes (d = 3: N = 32, 24, 20 with lines that straddle the
-    16-row MFMA blocks, ragged 13; d = 4: N = 24 and ragged 21, both N4 = 24)."""
+    16-row MFMA blocks, ragged 13; d = 4: N = 24 and ragged 21, both N4 = 24)
+    and every d = 3 padding of the split bfloat16 form (N4 = 20..32, with N a
+    multiple of 4 and not: 18, 27, 28, 30)."""
     say("mixed one step smooth", d, N)
     g = W.make_game(d, N, seed=60 + d + N, per_player=True)
     p1 = 0.5 * g.p_max * (np.cos(np.pi * np.arange(N) / (N - 1)) + 1.0)
@@ -132,9 +135,11 @@ def _basis(n, x):
     return V, D
 
 
-def test_one_step_within_a_priori_bound(cg, orc):
-    """One mixed step from a smooth state (the oracle's iterate after 12
-    steps) against the oracle's step, per sampled (player, node), within
+@pytest.mark.parametrize("N", [12, 24])
+def test_one_step_within_a_priori_bound(cg, orc, N):
+    """One mixed step from a smooth state (N = 12: the oracle's iterate after
+    12 steps; N = 24: a seeded smooth state) against the oracle's step, per
+    sampled (player, node), within
 
         |dV| <= delta * sum_{k_i} max_line |T_{k_i}| * |dw_{k_i}|,
         |dw_{k_i}| <= (4 u + gamma_{4 N4}(u)) * sum_K S_K |c[K, k_i]|   (u = 2^-24),
@@ -150,26 +155,44 @@ def test_one_step_within_a_priori_bound(cg, orc):
     products summed in binary32 over at most four outer values (4 N4 K-rows)
     and then in FP64.  The terms are bounded by magnitude (hence S).  A_2
     and the coefficients come from numpy and the oracle.  The FP64 rest of
-    the step adds its own budget, 1e-13 max|V|."""
-    g = W.make_game(3, 12, seed=9, per_player=True)
-    V, U, _ = orc.solve(g, 12)
-    Vo, Uo, _, _ = orc.step(g, V, U)
+    the step adds its own budget, 1e-13 max|V|.
+
+    From N4 = 20 on (N = 24 here) the D_a D_c product runs in the split
+    bfloat16 form: D_c and the coefficient, each rounded to binary32 once,
+    are split exactly into three bfloat16 pieces, the three dropped piece
+    products are below 2 u |D_c c| (each piece is at most 2^-8 of what it
+    splits), the 6 x 32 kept products of an outer value are summed in
+    binary32, multiplied by the rounded D_a (one rounding) and summed over
+    the N4 outer values in binary32: factor 6 u + gamma_{6 * 32 + N4}(u)."""
+    d = 3
+    g = W.make_game(d, N, seed=9, per_player=True)
+    x1 = orc.nodes(N)
+    p1 = 0.5 * g.p_max * (x1 + 1)
+    if N == 12:
+        V, U, _ = orc.solve(g, 12)
+    else:
+        V, U = W.smooth_state(g, p1, seed=9)
+    idx = np.arange(48, dtype=np.uint64)
+    players = (W.uniform(9, 3, idx) * d).astype(int)
+    nodes = (W.uniform(9, 4, idx) * N ** d).astype(int)
+    Vs, _ = orc.step_sample(g, V, U, players, nodes)
+    Vo = np.full_like(V, np.nan)
+    Vo[players, nodes] = Vs
+    vmax = np.max(np.abs(V))
     G = cg.ChebGame(g, cg.FP32_CORR)
     G.set_state(dev(V), dev(U))
     G.step(1)
     Vg = G.get_state()[0].cpu().numpy()
-    N, d = g.N, g.d
-    x1 = orc.nodes(N)
-    p1 = 0.5 * g.p_max * (x1 + 1)
     M = np.asarray(g.K) / np.asarray(g.m)[:, None] - np.diag(g.c)
     delta = 1 - g.rho * g.h
     u32 = 2.0 ** -24
     N4 = (N + 3) // 4 * 4
-    KS = 4 * N4                       # K-rows summed in binary32 before FP64
-    factor = 4 * u32 + KS * u32 / (1 - KS * u32)
-    idx = np.arange(48, dtype=np.uint64)
-    players = (W.uniform(9, 3, idx) * d).astype(int)
-    nodes = (W.uniform(9, 4, idx) * N ** d).astype(int)
+    if N4 >= 20:                      # split bfloat16 form
+        KS = 6 * 32 + N4
+        factor = 6 * u32 + KS * u32 / (1 - KS * u32)
+    else:
+        KS = 4 * N4                   # K-rows summed in binary32 before FP64
+        factor = 4 * u32 + KS * u32 / (1 - KS * u32)
     worst_ratio = 0.0
     for i, j in zip(players, nodes):
         coef = orc.transform(V[i].reshape((N,) * d))
@@ -195,7 +218,7 @@ def test_one_step_within_a_priori_bound(cg, orc):
         xi = 2 * (p[i] + g.h * (b[i] + g.beta[i] * (np.array([0.0, g.u_max]) - U[i, j]))) / g.p_max - 1
         Tmax = np.maximum(np.abs(npc.chebvander(xi, N - 1)).max(axis=0), 1.0)
         # binary32 share plus the FP64 share (the FP64 path's own bar)
-        bound = delta * np.sum(Tmax * dw) + 1e-13 * np.max(np.abs(Vo))
+        bound = delta * np.sum(Tmax * dw) + 1e-13 * vmax
         err = abs(Vg[i, j] - Vo[i, j])
         worst_ratio = max(worst_ratio, err / bound)
         assert err <= bound, (i, j, err, bound)
