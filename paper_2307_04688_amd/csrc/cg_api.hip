@@ -173,6 +173,26 @@ void diff_matrix(int N, const double *Dx, const double *x, double *Dd)
     }
 }
 
+// Basis at the nodes: TnP[j][k] = (T_k(x_j), T_k'(x_j)) for k < N, by the
+// three-term recurrences in long double from the (double) node x_j, then
+// rounded; zero for k >= N and j >= N.
+void node_basis(int N, const double *x, double *TnP)
+{
+    for (int e = 0; e < kMaxN * kMaxN * 2; ++e) TnP[e] = 0.0;
+    for (int j = 0; j < N; ++j) {
+        const long double xj = x[j];
+        long double t0 = 1.0L, t1 = xj, p0 = 0.0L, p1 = 1.0L;
+        for (int k = 0; k < N; ++k) {
+            double *e = TnP + 2 * (j * kMaxN + k);
+            if (k == 0) { e[0] = 1.0; e[1] = 0.0; continue; }
+            e[0] = (double)t1;
+            e[1] = (double)p1;
+            const long double t2 = 2.0L * xj * t1 - t0, p2 = 2.0L * t1 + 2.0L * xj * p1 - p0;
+            t0 = t1; t1 = t2; p0 = p1; p1 = p2;
+        }
+    }
+}
+
 }  // namespace
 
 struct cg_game {
@@ -197,11 +217,13 @@ struct cg_game {
 };
 
 namespace cg {
-void default_tiles(int d, int precision, int &rb, int &ocb)
+void default_tiles(int d, int N4, int precision, int &rb, int &ocb)
 {
-    // measured: d = 3, N = 32: FP64 fastest at (2, 2), FP32_CORR at (1, 2);
-    // d = 4, N = 24: FP64 at (1, 1), FP32_CORR at (1, 2)
-    rb = (precision == CG_FP32_CORR || d == 4) ? 1 : 2;
+    // measured: d = 3, N = 32: FP64 fastest at (2, 2), FP32_CORR in the split
+    // bfloat16 form at (2, 2) (44.5 against 45.6 us at (1, 2)), binary32 form
+    // at (1, 2); d = 4, N = 24: FP64 at (1, 1), FP32_CORR at (1, 2)
+    const bool split = precision == CG_FP32_CORR && corr3_split16(d, N4);
+    rb = split ? 2 : ((precision == CG_FP32_CORR || d == 4) ? 1 : 2);
     ocb = d >= 3 && !(d == 4 && precision != CG_FP32_CORR) ? 2 : 1;
 }
 const GameConst &game_consts(const cg_game *g) { return g->hc; }
@@ -358,6 +380,7 @@ void build_consts(const cg_game_desc *g, GameConst &hc)
     dct1_matrix(Nu, hc.Du);
     dct1_matrix(N, hc.Dx);
     diff_matrix(N, hc.Dx, hc.xnode, hc.Dd);
+    node_basis(N, hc.xnode, hc.TnP);
 }
 
 }  // namespace
@@ -427,7 +450,7 @@ int cg_init_game(const cg_game_desc *g, int precision, void *ws_dev, size_t ws_b
     b.ev_begin = b.ev_end = nullptr;
     b.tab = (const Inst *)(G->ws + L.tab);
     b.count = 1;
-    default_tiles(hc.d, precision, b.rb, b.ocb);
+    default_tiles(hc.d, hc.N4, precision, b.rb, b.ocb);
     InstPtrs &hi = G->inst;
     hi.gc = b.gc;
     hi.st = b.status;

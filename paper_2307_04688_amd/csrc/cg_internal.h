@@ -34,6 +34,8 @@ struct GameConst {
     double Dx[kMaxN * kMaxN];  // DCT-I matrix of the state transform, [l][k]
     double Dd[kMaxN * kMaxN];  // nodal differentiation: derivative at node j of the
                                // interpolant of nodal values, [j][k] (normalised x)
+    double TnP[kMaxN * kMaxN * 2];  // basis at the nodes, [j][k][2]: T_k(x_j), T_k'(x_j)
+                                    // (k < N; zero past N)
 };
 
 // d = 3 mixed contraction: floats per lane of one nodal tensor slab stored
@@ -203,7 +205,7 @@ const InstPtrs &game_inst(const cg_game *g);
 int game_precision(const cg_game *g);
 hipStream_t game_stream(const cg_game *g);
 // Default contraction tile shapes (row blocks per wave, outer values per slab).
-void default_tiles(int d, int precision, int &rb, int &ocb);
+void default_tiles(int d, int N4, int precision, int &rb, int &ocb);
 // Records an error message for cg_last_error(); returns code.
 int set_error(int code, const char *msg);
 // CG_OK if the current device is a gfx950, else CG_EDEVICE with a message.

@@ -223,6 +223,28 @@ struct ModeRec4 {
     }
 };
 
+// T_k(x) alone for k = k0, k0 + 4, ... (the node values come from a table).
+struct ModeT4 {
+    double t4, t0, t1;  // T_4; T_{k-4}, T_k
+    __device__ void init(double x, int k0)
+    {
+        double T[5];
+        T[0] = 1.0; T[1] = x;
+#pragma unroll
+        for (int k = 1; k < 4; ++k) T[k + 1] = 2.0 * x * T[k] - T[k - 1];
+        t4 = T[4];
+        t1 = T[0]; t0 = T[4];
+#pragma unroll
+        for (int m = 1; m < 4; ++m)
+            if (k0 == m) { t1 = T[m]; t0 = T[4 - m]; }
+    }
+    __device__ void advance4()
+    {
+        const double tn = 2.0 * t4 * t1 - t0;
+        t0 = t1; t1 = tn;
+    }
+};
+
 template <int D, int N4, int NC, int RB, int OCB>
 __global__ __launch_bounds__(256) void k_contract_corr(const Inst *__restrict__ tab, int bpi,
                                                        int blocks_per_player)
@@ -500,7 +522,9 @@ __global__ __launch_bounds__(256) void k_contract_corr(const Inst *__restrict__ 
 // 16 rows of an MFMA block share (jo, jn) when N is a multiple of 16; a block
 // that straddles lines runs the E2 terms once per line, the A rows of the
 // other lines masked to zero.  binary32 partial sums enter FP64 every FOLD
-// slabs (FOLD OCB N4 K-rows), in the split form once after the last slab.
+// slabs (FOLD OCB N4 K-rows); in the split form the whole remainder (one-mode
+// terms and every outer value) is summed in binary32 and enters FP64 in the
+// epilogue.
 // Slab sb (OCB outer values) of the packed binary32 coefficients into
 // registers: float4 element e4 = tid + NTHR q of the slab.  Outer values past
 // the last one (slabs padded to whole groups) read the last one's
@@ -627,6 +651,17 @@ void k_contract_corr3(
         const int L = divN(r), ji = r - L * N;
         const int jo = divN(L), jn = L - jo * N;
         const int j = ji * st_i + jo * st_o + jn * st_n;
+        // T_k and T_k' at the node from the table (this lane's k = 4 t + kq,
+        // zero past N), loaded before the node state so that the two round
+        // trips overlap
+        const double2 *tbo = reinterpret_cast<const double2 *>(gc->TnP) + jo * kMaxN + kq;
+        const double2 *tbn = reinterpret_cast<const double2 *>(gc->TnP) + jn * kMaxN + kq;
+        double2 bo[NT], bn[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            bn[t] = tbn[4 * t];
+            bo[t] = tbo[4 * t];
+        }
         double p[D], ub[D], b[D];
         node_state<D>(gc, Uold, j, p, ub, b);
         double xo = 0.0, xn = 0.0;
@@ -642,42 +677,46 @@ void k_contract_corr3(
             dls[rl * 2 + 0] = xo - xbo;
             dls[rl * 2 + 1] = xn - xbn;
         }
-        ModeRec4 mo, mn;
-        mo.init(xo, xbo, kq);
-        mn.init(xn, xbn, kq);
+        // T_k at the shifted point by recurrence
+        ModeT4 mo, mn;
+        mo.init(xo, kq);
+        mn.init(xn, kq);
+        const double dlo = xo - xbo, dln = xn - xbn;
+        float *dOl = SPLIT ? dO + kq * LDT + rl : dO + rl * LDO + kq;
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
-            double T, Tb, P, R1;
-            mn.get(T, Tb, P, R1);
-            Dn[rb][t] = (float)(T - Tb);
-            R1n[rb][t] = (float)R1;
+            const int k = 4 * t + kq;
+            const double Dnk = mn.t1 - bn[t].x;   // D = T - Tb
+            Dn[rb][t] = (float)Dnk;
+            R1n[rb][t] = (float)(Dnk - bn[t].y * dln);  // R1 = D - T'(xbar) Delta
             mn.advance4();
-            mo.get(T, Tb, P, R1);
-            R1o[rb][t] = (float)R1;
-            const float dov = 4 * t + kq < N ? (float)(T - Tb) : 0.f;  // outer values past N: zero rows
-            if constexpr (SPLIT)
-                dO[(4 * t + kq) * LDT + rl] = dov;
-            else
-                dO[rl * LDO + 4 * t + kq] = dov;
+            const double Dok = mo.t1 - bo[t].x;
+            R1o[rb][t] = (float)(Dok - bo[t].y * dlo);
+            const float dov = k < N ? (float)Dok : 0.f;  // outer values past N: zero rows
+            dOl[SPLIT ? 4 * t * LDT : 4 * t] = dov;
             mo.advance4();
         }
     }
 
+    // binary32 form: acc holds one group of outer values, acc64 the FP64
+    // sum; split form: acc holds the whole remainder in binary32 (the one-mode
+    // terms, then every outer value) and acc64 is unused
     f32x4 acc[RB][NCB];
     double acc64[RB][NCB][4];
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-        for (int c = 0; c < NCB; ++c)
+        for (int c = 0; c < NCB; ++c) {
+            acc[rb][c] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int v = 0; v < 4; ++v) acc64[rb][c][v] = 0.0;
+        }
 
     // FOLD slabs per group (FOLD OCB = 4 outer values; the last group is
     // padded with zero rows of A): the first MFMA of a group starts from a
     // zero accumulator and the group's binary32 sums then enter FP64, with no
-    // branch inside the group; FOLD is even (or OCB FOLD slabs of one) so the
-    // LDS buffer of slab q is fixed.
-    static_assert(OCB * FOLD == 4 && (FOLD % 2 == 0), "four outer values per group, even FOLD");
+    // branch inside the group; slab sb sits in LDS buffer sb mod 2.
+    static_assert(OCB * FOLD == 4, "four outer values per group");
     const int n_groups = (n_outer + OCB * FOLD - 1) / (OCB * FOLD);
     const int n_slabs = n_groups * FOLD;
     if constexpr (SPLIT)
@@ -721,7 +760,12 @@ void k_contract_corr3(
 #pragma unroll
             for (int c = 0; c < NCB; ++c)
 #pragma unroll
-                for (int v = 0; v < 4; ++v) acc64[rb][c][v] += (double)na[c][v];
+                for (int v = 0; v < 4; ++v) {
+                    if constexpr (SPLIT)
+                        acc[rb][c][v] += na[c][v];
+                    else
+                        acc64[rb][c][v] += (double)na[c][v];
+                }
         }
     }
 
@@ -734,6 +778,10 @@ void k_contract_corr3(
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
                 float r = e < NT ? Dn[rb][e] : 0.f;
+                // the pieces split the binary32 value (an opaque copy keeps the
+                // compiler from rounding the FP64 value to bf16 directly, a
+                // longer sequence)
+                __asm__("" : "+v"(r));
 #pragma unroll
                 for (int p = 0; p < 3; ++p) {
                     const __bf16 h = (__bf16)r;
@@ -758,7 +806,7 @@ void k_contract_corr3(
 #pragma unroll
                 for (int ocl = 0; ocl < OCB; ++ocl) {
                     const int oc = sb * OCB + ocl;
-                    const f32x4 *fb = reinterpret_cast<const f32x4 *>(lds + (q & 1) * SLAB) + ocl * OC_E4 + lane;
+                    const f32x4 *fb = reinterpret_cast<const f32x4 *>(lds + (sb & 1) * SLAB) + ocl * OC_E4 + lane;
                     bf16x8 b16[3][NCB];
 #pragma unroll
                     for (int p = 0; p < 3; ++p)
@@ -792,7 +840,7 @@ void k_contract_corr3(
 #pragma unroll
             for (int ocl = 0; ocl < OCB; ++ocl) {
                 const int oc = sb * OCB + ocl;
-                const float *cb = lds + (q & 1) * SLAB + ocl * N4 * LDB;
+                const float *cb = lds + (sb & 1) * SLAB + ocl * N4 * LDB;
                 float bf[NT][NCB];
 #pragma unroll
                 for (int t = 0; t < NT; ++t)
@@ -819,9 +867,9 @@ void k_contract_corr3(
             }
             if (more) {
                 if constexpr (SPLIT)
-                    corr3_store_flat<PF, SLAB_E4, NTHR>(pf, lds + ((q + 1) & 1) * SLAB, tid);
+                    corr3_store_flat<PF, SLAB_E4, NTHR>(pf, lds + ((sb + 1) & 1) * SLAB, tid);
                 else
-                    corr3_store<PF, SLAB_E4, NC, LDB, NTHR>(pf, lds + ((q + 1) & 1) * SLAB, tid);
+                    corr3_store<PF, SLAB_E4, NC, LDB, NTHR>(pf, lds + ((sb + 1) & 1) * SLAB, tid);
             }
             __syncthreads();
         }
@@ -836,25 +884,16 @@ void k_contract_corr3(
     };
     if constexpr (SPLIT) {
         // the split form sums every outer value in binary32 (the 6 x 32 piece
-        // products of one outer value already are) and enters FP64 once
-#pragma unroll
-        for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-            for (int c = 0; c < NCB; ++c) acc[rb][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+        // products of one outer value already are) and enters FP64 in the
+        // epilogue
 #pragma unroll 1
         for (int g = 0; g < n_groups; ++g) run_group(g);
-#pragma unroll
-        for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-            for (int c = 0; c < NCB; ++c)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) acc64[rb][c][v] += (double)acc[rb][c][v];
     } else {
         for (int g = 0; g < n_groups; ++g) run_group(g);
     }
 
     // ---- epilogue: element v of lane c + 16 kq is row 4 kq + v (f32 layout);
-    //      W = acc64 + E0 + Delta_o E1_o + Delta_n E1_n ----
+    //      W = remainder + E0 + Delta_o E1_o + Delta_n E1_n ----
     const double *Ei = I.E + (long long)player * D * NM * NC;
     double *Wp = I.W + (long long)player * NN * NC;
 #pragma unroll
@@ -887,7 +926,7 @@ void k_contract_corr3(
                     e1o[c] = Ei[((long long)NM + L) * NC + col];
                     e1n[c] = Ei[((long long)2 * NM + L) * NC + col];
                 }
-                double w = acc64[rb][c][v] + e0[c];
+                double w = (SPLIT ? (double)acc[rb][c][v] : acc64[rb][c][v]) + e0[c];
                 w = fma(dlo, e1o[c], w);
                 w = fma(dln, e1n[c], w);
                 Wp[(long long)j * NC + col] = w;

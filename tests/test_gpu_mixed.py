@@ -162,8 +162,9 @@ def test_one_step_within_a_priori_bound(cg, orc, N):
     are split exactly into three bfloat16 pieces, the three dropped piece
     products are below 2 u |D_c c| (each piece is at most 2^-8 of what it
     splits), the 6 x 32 kept products of an outer value are summed in
-    binary32, multiplied by the rounded D_a (one rounding) and summed over
-    the N4 outer values in binary32: factor 6 u + gamma_{6 * 32 + N4}(u)."""
+    binary32, multiplied by the rounded D_a (one rounding) and summed in
+    binary32 over the N4 outer values, onto the one-mode terms (2 N4 binary32
+    products): factor 6 u + gamma_{6 * 32 + 3 N4}(u)."""
     d = 3
     g = W.make_game(d, N, seed=9, per_player=True)
     x1 = orc.nodes(N)
@@ -188,7 +189,7 @@ def test_one_step_within_a_priori_bound(cg, orc, N):
     u32 = 2.0 ** -24
     N4 = (N + 3) // 4 * 4
     if N4 >= 20:                      # split bfloat16 form
-        KS = 6 * 32 + N4
+        KS = 6 * 32 + 3 * N4
         factor = 6 * u32 + KS * u32 / (1 - KS * u32)
     else:
         KS = 4 * N4                   # K-rows summed in binary32 before FP64
