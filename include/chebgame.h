@@ -48,8 +48,12 @@ extern "C" {
  * rounded to binary32 / bfloat16, products accumulated in binary32 on MFMA.
  * CG_FP32_CORR (games only): the contraction is split into an FP64 part
  * (value and first-order Taylor term at the node, computed by small mode
- * products) and a second-order remainder contracted on binary32 MFMA; the
- * transform, line fit, argmax, step accumulation and residual stay FP64. */
+ * products) and a second-order remainder contracted at binary32 accuracy on
+ * MFMA: for d = 3 with N rounded up to a multiple of 4 at least 20, both
+ * operands are rounded to binary32 and split exactly into three bfloat16
+ * pieces, and the six leading piece products run on bf16 MFMA with binary32
+ * sums; otherwise on binary32 MFMA.  The transform, line fit, argmax, step
+ * accumulation and residual stay FP64. */
 #define CG_FP64 0
 #define CG_FP32 1
 #define CG_BF16 2
@@ -319,10 +323,11 @@ int cg_profile(cg_game *game, int enable, double *kernel_ms, int64_t *launches);
 
 /* Tile shapes of the game's contraction kernel: rb row blocks of 16 nodes per
  * wave (1, 2 or 4) and ocb values of the outer modes per coefficient slab
- * (1 or 2; 1 when d = 2).  Defaults: rb = 2 (CG_FP32_CORR: 1), ocb = 2 (d = 2:
- * 1).  Results do not depend on
- * rb; ocb changes where the binary32 partial sums of CG_FP32_CORR enter
- * FP64.  CG_EINVAL for other values. */
+ * (1 or 2; 1 when d = 2).  Defaults: rb = 2 (CG_FP32_CORR: 1, or 2 in the
+ * split bfloat16 form), ocb = 2 (d = 2: 1).  Results do not depend on rb;
+ * ocb changes where the binary32 partial sums of CG_FP32_CORR enter FP64
+ * (not in the split bfloat16 form, whose remainder enters FP64 once).
+ * CG_EINVAL for other values. */
 int cg_set_tiles(cg_game *game, int32_t rb, int32_t ocb);
 
 /* ------------------------------------------------------------------------

@@ -1,5 +1,7 @@
-// cg_mixed.hip -- contraction of the value-iteration step with binary32 MFMA
-// and an FP64 correction (precision CG_FP32_CORR).
+// cg_mixed.hip -- contraction of the value-iteration step at binary32
+// accuracy on MFMA (binary32 MFMA, or for d = 3 from N4 = 20 on bf16 MFMA on
+// exactly split binary32 operands) with an FP64 correction (precision
+// CG_FP32_CORR).
 //
 // For player i and node j with other-mode coordinates x_l = xbar_l + Delta_l
 // (xbar_l the node, Delta_l = 2 h b_l / p_max the Euler shift), the line
@@ -10,13 +12,13 @@
 //   R   = sum_K A2_K c_i[K],  A2 = KR(x) - KR(xbar) - sum_l Delta_l d/dx_l KR(xbar).
 // E0 and E1 are small FP64 mode products of V (no point evaluation), computed
 // once per iteration; only the second-order remainder R, of relative size
-// ~Delta^2, runs on binary32 MFMA (inputs rounded to binary32, products
-// accumulated in binary32 over a few LDS slabs -- at most 4 N4 K-rows --
-// then added into FP64).
+// ~Delta^2, runs at binary32 accuracy (inputs rounded to binary32, products
+// accumulated in binary32, then added into FP64).
 //
 // Two kernels contract R.  d = 3 (k_contract_corr3): the remainder splits
-// into one binary32 product per K element plus two one-mode contractions
-// against nodal tensors (see the kernel).  d = 2, 4 (k_contract_corr): A2 is
+// into one product per K element plus two one-mode contractions against
+// nodal tensors, the products in split bfloat16 form from N4 = 20 on (see
+// the kernel).  d = 2, 4 (k_contract_corr): A2 is
 // built per K element from per-mode quantities: with T = T_k(x),
 // Tb = T_k(xbar), P = T_k'(xbar) Delta (first-order increment) and
 // R1 = T - Tb - P, a product over a mode set S extends by a mode c as
