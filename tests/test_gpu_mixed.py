@@ -241,3 +241,27 @@ def test_mixed_checkpoint_and_symmetry(cg):
     assert torch.equal(Va, Vc) and torch.equal(Ua, Uc)
     Vn = Va.cpu().numpy().reshape(3, 12, 12, 12)
     assert np.max(np.abs(Vn[0] - np.transpose(Vn[2], (2, 1, 0)))) <= 1e-10 * np.max(np.abs(Vn))
+
+
+@pytest.mark.parametrize("d,N,prec,tiles", [
+    (3, 24, "FP32_CORR", [(2, 2), (1, 2), (1, 1), (2, 1), (4, 2)]),   # split bfloat16 form
+    (3, 30, "FP32_CORR", [(2, 2), (1, 1), (4, 1)]),                   # split form, N != N4
+    (3, 32, "FP64", [(2, 2), (1, 2), (4, 2)]),
+])
+def test_tiles_do_not_change_results(cg, d, N, prec, tiles):
+    """The contraction's tile shapes (cg_set_tiles: row blocks per wave, outer
+    values per slab) change only the schedule: every shape gives bitwise the
+    same iterate, for the FP64 path over rb and for the split bfloat16 form of
+    the mixed path over rb and ocb (its remainder sums the outer values in
+    order and enters FP64 once)."""
+    g = W.make_game(d, N, seed=80 + N, per_player=True)
+    out = []
+    for rb, ocb in tiles:
+        G = cg.ChebGame(g, getattr(cg, prec))
+        G.set_tiles(rb, ocb)
+        G.step(4)
+        V, U, _ = G.get_state()
+        out.append((V.cpu(), U.cpu()))
+        G.destroy()
+    for (V, U), t in zip(out[1:], tiles[1:]):
+        assert torch.equal(V, out[0][0]) and torch.equal(U, out[0][1]), t
