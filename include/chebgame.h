@@ -58,6 +58,12 @@ extern "C" {
 #define CG_FP32 1
 #define CG_BF16 2
 #define CG_FP32_CORR 3
+/* cg_chebyshev_eval only: binary32 accuracy on the bf16 MFMA.  Basis
+ * products and coefficients rounded to binary32 and split exactly into three
+ * bfloat16 pieces; the six piece products of leading order (hi hi, hi mid,
+ * mid hi, hi lo, mid mid, lo hi; the three dropped ones are below 2^-24 of
+ * the product) accumulated in binary32.  Output float, like CG_FP32. */
+#define CG_FP32_SPLIT 4
 
 /* Sizes compiled into the library. */
 #define CG_MAX_D 4   /* players (state dimension) */
@@ -137,7 +143,7 @@ int cg_chebyshev_transform(int d, const int32_t *n, const double *vals_dev, doub
  * in Section 3.2) at npts points.  coef_dev: shape n[0] x ... x n[d-1] FP64;
  * x_dev: npts x d FP64 row-major, normalised coordinates (points outside
  * [-1,1]^d are evaluated by polynomial continuation); out_dev: npts values,
- * double for CG_FP64, float for CG_FP32 and CG_BF16.  1 <= d <= CG_MAX_D,
+ * double for CG_FP64, float for CG_FP32, CG_BF16 and CG_FP32_SPLIT.  1 <= d <= CG_MAX_D,
  * 2 <= n[l] <= CG_MAX_N.  Needs cg_eval_workspace_bytes() bytes of device
  * workspace in ws_dev.  Queued on 'stream'. */
 size_t cg_eval_workspace_bytes(int d, const int32_t *n, int precision);

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "libchebgame.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "chebgame.h")
 
 OK, ENOTCONVERGED, EINVAL, EUNSUPPORTED, EDEVICE, ENOMEM, ENONFINITE = 0, 1, -1, -2, -3, -4, -5
-FP64, FP32, BF16, FP32_CORR = 0, 1, 2, 3
+FP64, FP32, BF16, FP32_CORR, FP32_SPLIT = 0, 1, 2, 3, 4
 MAX_D, MAX_N = 4, 32
 
 

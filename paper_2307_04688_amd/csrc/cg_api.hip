@@ -580,7 +580,7 @@ int check_eval_args(int d, const int32_t *n, const double *coef_dev, const doubl
     if (d < 1 || d > CG_MAX_D) return fail(CG_EUNSUPPORTED, "d = %d outside [1, %d]", d, CG_MAX_D);
     if (npts < 0) return fail(CG_EINVAL, "npts < 0");
     if (!n || !coef_dev || (npts > 0 && (!x_dev || !out_dev))) return fail(CG_EINVAL, "NULL argument");
-    if (precision != CG_FP64 && precision != CG_FP32 && precision != CG_BF16)
+    if (precision != CG_FP64 && precision != CG_FP32 && precision != CG_BF16 && precision != CG_FP32_SPLIT)
         return fail(CG_EUNSUPPORTED, "eval precision %d not supported", precision);
     for (int l = 0; l < d; ++l) {
         if (n[l] < 2 || n[l] > CG_MAX_N) return fail(CG_EUNSUPPORTED, "n[%d] = %d outside [2, %d]", l, n[l], CG_MAX_N);

@@ -6,8 +6,11 @@
 // where row q of KR is the Khatri-Rao product of the basis vectors
 // (T_k(x_{q,l}))_k and C is the coefficient tensor with the last mode as
 // columns; then f(x_q) = sum_k W[q,k] T_k(x_{q,d-1}) by Clenshaw.  The GEMM
-// runs on MFMA: f64 16x16x4 (CG_FP64), f32 16x16x4 (CG_FP32) or bf16
-// 16x16x32 with f32 accumulation (CG_BF16).
+// runs on MFMA: f64 16x16x4 (CG_FP64), f32 16x16x4 (CG_FP32), or bf16
+// 16x16x32 with f32 accumulation (CG_BF16; CG_FP32_SPLIT with both operands
+// as three exact bf16 pieces of their binary32 values).
+#include <type_traits>
+
 #include "cg_internal.h"
 #include "cg_line.h"
 
@@ -217,6 +220,12 @@ __global__ __launch_bounds__(256) void k_eval_mfma(const TE *__restrict__ Bp, co
 // chunk of KSC = 18 steps is three slabs per o), written by direct
 // global-to-LDS loads into a ring of three slabs two ahead of the MFMAs,
 // with one barrier per slab.  The per-row basis tables live in LDS.
+//
+// The same kernel gives binary32 accuracy on the bf16 MFMA (CG_FP32_SPLIT,
+// three pieces): the basis products and coefficients are rounded to binary32
+// and split exactly into three bf16 pieces each (at most two K-steps per
+// chunk, one per slab), and every K-step runs the six piece products of
+// leading order; the tables stay in binary32.
 struct Bf16Geo {
     int n_o, n_b, n_l, n_c;  // outer mode, second inner mode (1 if none), mode d-2, last mode
     int K2, CH;              // inner length n_b * N4, chunks of 32 KSC
@@ -224,21 +233,28 @@ struct Bf16Geo {
 };
 
 // K-steps per slab for a chunk of KSC steps; a chunk is KSC / KP slabs per o.
-__host__ __device__ constexpr int bf16_kp(int ksc) { return ksc <= 6 ? ksc : 6; }
+// The split form (np = 3 pieces) takes one K-step per slab: its ring then
+// leaves room for two blocks per CU beside the binary32 tables (measured at
+// d = 4, N = 24: 13.9 against 23.8 ms with two steps per slab).
+__host__ __device__ constexpr int bf16_kp(int ksc, int np = 1) { return np > 1 ? 1 : (ksc <= 6 ? ksc : 6); }
 
-// Packed C: fragment-contiguous, ((((o CH + ch) KSC + ks) NCB + c) 4 + g) 16 + col, 8 bf16 each,
-// for o < n_og OG (zero beyond n_o).
-template <int KSC, int NCB>
+// Packed C: fragment-contiguous, (((((o CH + ch) KSC + ks) NP + piece) NCB + c) 4 + g) 16 + col,
+// 8 bf16 each, for o < n_og OG (zero beyond n_o).  NP = 1: the coefficient
+// rounded to bf16; NP = 3 (split form): the coefficient rounded to binary32
+// as three bf16 pieces whose sum is that binary32 value exactly.
+template <int KSC, int NCB, int NP>
 __global__ __launch_bounds__(256) void k_pack_bf16(const double *__restrict__ coef, __bf16 *__restrict__ Bp,
                                                    Bf16Geo gg, int N4)
 {
-    const long long total = (long long)gg.n_og * gg.OG * gg.CH * KSC * NCB * 512;
+    const long long total = (long long)gg.n_og * gg.OG * gg.CH * KSC * NP * NCB * 512;
     const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= total) return;
     const int ee = (int)(e & 7), col = (int)((e >> 3) & 15), g = (int)((e >> 7) & 3);
     long long r = e >> 9;
     const int c = (int)(r % NCB);
     r /= NCB;
+    const int piece = (int)(r % NP);
+    r /= NP;
     const int ks = (int)(r % KSC);
     r /= KSC;
     const int ch = (int)(r % gg.CH);
@@ -251,7 +267,16 @@ __global__ __launch_bounds__(256) void k_pack_bf16(const double *__restrict__ co
         if (kl < gg.n_l && colf < gg.n_c)
             v = coef[(((long long)o * gg.n_b + kb) * gg.n_l + kl) * gg.n_c + colf];
     }
-    Bp[e] = (__bf16)(float)v;
+    float f = (float)v;
+    if constexpr (NP > 1) __asm__("" : "+v"(f));  // the pieces split the binary32 value
+    __bf16 h = (__bf16)f;
+#pragma unroll
+    for (int q = 1; q < NP; ++q) {
+        if (q > piece) break;
+        f -= (float)h;  // exact: what the previous pieces left
+        h = (__bf16)f;
+    }
+    Bp[e] = h;
 }
 
 // s_waitcnt vmcnt(N) lgkmcnt(0), no wait on expcnt (gfx9 encoding:
@@ -263,15 +288,22 @@ __device__ __forceinline__ void wait_vmcnt()
     __builtin_amdgcn_s_waitcnt(0x0070 | N);
 }
 
-template <int D, int N4, int NC, int KSC>
+template <int D, int N4, int NC, int KSC, int NP>
 __global__ __launch_bounds__(256) void k_eval_bf16(const __bf16 *__restrict__ Bp, const double *__restrict__ X,
                                                    float *__restrict__ out, long long npts, Bf16Geo gg)
 {
+    // NP = 1: bf16 operands; NP = 3 (split form): both operands rounded to
+    // binary32 and split exactly into three bf16 pieces, and the six piece
+    // products of leading order (the three dropped ones are below 2^-24 of
+    // the product) summed in binary32
+    static_assert(NP == 1 || NP == 3, "one or three pieces");
+    constexpr int NPP = NP == 3 ? 6 : 1;          // piece products per K-step
+    constexpr int PD = NP == 1 ? 2 : 1;           // fragment reads run PD K-steps ahead
     constexpr int NCB = NC / 16;
     constexpr int RB = 2;                         // 16-row blocks per wave
     constexpr int ROWS_W = RB * 16;
     constexpr int ROWS_B = 4 * ROWS_W;            // 128 points per block of four waves
-    constexpr int KP = bf16_kp(KSC);              // K-steps per slab
+    constexpr int KP = bf16_kp(KSC, NP);          // K-steps per slab
     constexpr int NPART = KSC / KP;               // slabs per (chunk, o)
     static_assert(NPART * KP == KSC, "a chunk is whole slabs");
     constexpr int LDT = N4;                       // mode-l table stride (floats; 16-byte rows)
@@ -280,14 +312,16 @@ __global__ __launch_bounds__(256) void k_eval_bf16(const __bf16 *__restrict__ Bp
     constexpr int FRAG = 512;                     // bf16 per fragment (64 lanes x 16 bytes)
     constexpr int NBUF = 3;
     constexpr int LDW = NC + 1;
-    const int FR = (NPART > 1 ? 1 : gg.OG) * KP * NCB;  // fragments per slab (OG = 1 when NPART > 1)
+    const int FR = (NPART > 1 ? 1 : gg.OG) * KP * NP * NCB;  // fragments per slab (OG = 1 when NPART > 1)
     const int n_op = gg.n_og * gg.OG;             // outer values incl. padding
     // The tables are arrays of their own, apart from the ring that the
     // direct loads write, so that reading them waits for no load in flight.
     // The mode-1 factor is stored in binary16 (|T| <= 1; rounding 2^-12,
     // far below the bf16 rounding of the product it enters).
     __shared__ __attribute__((aligned(16))) float Tl[ROWS_B * LDT];
-    __shared__ _Float16 Tb[D == 4 ? ROWS_B * LDB : 1];
+    // (binary32 in the split form, whose products keep binary32 accuracy)
+    using TbT = typename std::conditional<NP == 1, _Float16, float>::type;
+    __shared__ TbT Tb[D == 4 ? ROWS_B * LDB : 1];
     __shared__ __attribute__((aligned(16))) float To[MAXO * ROWS_B];  // T_o(x_q0) as [o][row]
     extern __shared__ __attribute__((aligned(16))) __bf16 Bs[];        // NBUF slabs of FR fragments
     const int SLAB = FR * FRAG;
@@ -330,10 +364,10 @@ __global__ __launch_bounds__(256) void k_eval_bf16(const __bf16 *__restrict__ Bp
         } else if (D == 4 && tid < 2 * ROWS_B) {
             const float xb = (float)xq[1];
             float tm = 1.0f, tc = xb;
-            Tb[r * LDB] = (_Float16)1.0f;
+            Tb[r * LDB] = (TbT)1.0f;
 #pragma unroll 4
             for (int k = 1; k < LDB; ++k) {
-                Tb[r * LDB + k] = (_Float16)(k < gg.n_b ? tc : 0.0f);
+                Tb[r * LDB + k] = (TbT)(k < gg.n_b ? tc : 0.0f);
                 const float tn = fmaf(2.0f * xb, tc, -tm);
                 tm = tc;
                 tc = tn;
@@ -351,19 +385,19 @@ __global__ __launch_bounds__(256) void k_eval_bf16(const __bf16 *__restrict__ Bp
     int i_ch = 0, i_og = 0, i_p = 0, i_buf = 0;
     auto issue_next = [&]() {
         __bf16 *dst = Bs + i_buf * SLAB;
-        const int base = (((i_og * gg.OG) * gg.CH + i_ch) * KSC + i_p * KP) * NCB;
-        if (NPART > 1) {  // FR = KP NCB fragments, known here: unrolled
+        const int base = (((i_og * gg.OG) * gg.CH + i_ch) * KSC + i_p * KP) * NP * NCB;
+        if (NPART > 1) {  // FR = KP NP NCB fragments, known here: unrolled
 #pragma unroll
-            for (int j = 0; j < (KP * NCB + 3) / 4; ++j) {
+            for (int j = 0; j < (KP * NP * NCB + 3) / 4; ++j) {
                 const int f = wave + 4 * j;
-                if (f < KP * NCB)
+                if (f < KP * NP * NCB)
                     __builtin_amdgcn_global_load_lds(
                         Bl + (base + f) * FRAG, (__attribute__((address_space(3))) void *)(dst + f * FRAG), 16, 0, 0);
             }
         } else {
             for (int f = wave; f < FR; f += 4) {
-                const int oo = f / (KP * NCB), rest = f - oo * (KP * NCB);
-                const int src = base + oo * gg.CH * KSC * NCB + rest;
+                const int oo = f / (KP * NP * NCB), rest = f - oo * (KP * NP * NCB);
+                const int src = base + oo * gg.CH * KSC * NP * NCB + rest;
                 __builtin_amdgcn_global_load_lds(
                     Bl + src * FRAG, (__attribute__((address_space(3))) void *)(dst + f * FRAG), 16, 0, 0);
             }
@@ -383,7 +417,7 @@ __global__ __launch_bounds__(256) void k_eval_bf16(const __bf16 *__restrict__ Bp
     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
         for (int c = 0; c < NCB; ++c) W[rb][c] = f32x4{0.f, 0.f, 0.f, 0.f};
-    bf16x8 a[RB][KSC];
+    bf16x8 a[RB][KSC][NP];
 
     issue_next();
     if (nslab > 1) issue_next();
@@ -405,10 +439,18 @@ __global__ __launch_bounds__(256) void k_eval_bf16(const __bf16 *__restrict__ Bp
                     const float4 t = *reinterpret_cast<const float4 *>(Tl + r * LDT + kl0);
                     const float tb =
                         D == 4 ? (float)Tb[r * LDB + (kb < LDB - 1 ? kb : LDB - 1)] : (kb == 0 ? 1.0f : 0.0f);
-                    a[rb][ks][4 * h + 0] = (__bf16)(tb * t.x);
-                    a[rb][ks][4 * h + 1] = (__bf16)(tb * t.y);
-                    a[rb][ks][4 * h + 2] = (__bf16)(tb * t.z);
-                    a[rb][ks][4 * h + 3] = (__bf16)(tb * t.w);
+                    float pr[4] = {tb * t.x, tb * t.y, tb * t.z, tb * t.w};
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        float f = pr[u];
+                        if constexpr (NP > 1) __asm__("" : "+v"(f));  // the split starts from the binary32 product
+#pragma unroll
+                        for (int q = 0; q < NP; ++q) {
+                            const __bf16 hq = (__bf16)f;
+                            a[rb][ks][q][4 * h + u] = hq;
+                            f -= (float)hq;
+                        }
+                    }
                 }
         }
         for (int og = 0; og < gg.n_og; ++og) {
@@ -435,40 +477,50 @@ __global__ __launch_bounds__(256) void k_eval_bf16(const __bf16 *__restrict__ Bp
                 const __bf16 *sb = Bs + c_buf * SLAB + lane * 8;
                 c_buf = c_buf == NBUF - 1 ? 0 : c_buf + 1;
                 for (int oo = 0; oo < gg.OG; ++oo) {
-                    // fragment reads run two K-steps ahead of the MFMAs that
-                    // use them (an LDS read outlasts one K-step's four MFMAs)
-                    const __bf16 *so = sb + oo * KP * NCB * FRAG;
-                    bf16x8 b[3][NCB];
+                    // fragment reads run PD K-steps ahead of the MFMAs that
+                    // use them (an LDS read outlasts one K-step's MFMAs)
+                    const __bf16 *so = sb + oo * KP * NP * NCB * FRAG;
+                    bf16x8 b[PD + 1][NP][NCB];
 #pragma unroll
-                    for (int kk = 0; kk < 2 && kk < KP; ++kk)
+                    for (int kk = 0; kk < PD && kk < KP; ++kk)
 #pragma unroll
-                        for (int c = 0; c < NCB; ++c)
-                            b[kk][c] = *reinterpret_cast<const bf16x8 *>(so + (kk * NCB + c) * FRAG);
-#pragma unroll
-                    for (int kk = 0; kk < KP; ++kk) {
-                        if (kk + 2 < KP) {
+                        for (int q = 0; q < NP; ++q)
 #pragma unroll
                             for (int c = 0; c < NCB; ++c)
-                                b[(kk + 2) % 3][c] =
-                                    *reinterpret_cast<const bf16x8 *>(so + ((kk + 2) * NCB + c) * FRAG);
+                                b[kk][q][c] = *reinterpret_cast<const bf16x8 *>(so + ((kk * NP + q) * NCB + c) * FRAG);
+#pragma unroll
+                    for (int kk = 0; kk < KP; ++kk) {
+                        if (kk + PD < KP) {
+#pragma unroll
+                            for (int q = 0; q < NP; ++q)
+#pragma unroll
+                                for (int c = 0; c < NCB; ++c)
+                                    b[(kk + PD) % (PD + 1)][q][c] = *reinterpret_cast<const bf16x8 *>(
+                                        so + (((kk + PD) * NP + q) * NCB + c) * FRAG);
                         }
+                        // piece products (A piece, B piece), smallest first
+                        constexpr int PA[6] = {2, 1, 0, 1, 0, 0}, PB[6] = {0, 1, 2, 0, 1, 0};
 #pragma unroll
-                        for (int c = 0; c < NCB; ++c)
+                        for (int pp = 0; pp < NPP; ++pp)
 #pragma unroll
-                            for (int rb = 0; rb < RB; ++rb)  // each o starts from zero
-                                P[rb][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                                    a[rb][p * KP + kk], b[kk % 3][c],
-                                    (p == 0 && kk == 0) ? f32x4{0.f, 0.f, 0.f, 0.f} : P[rb][c], 0, 0, 0);
+                            for (int c = 0; c < NCB; ++c)
+#pragma unroll
+                                for (int rb = 0; rb < RB; ++rb)  // each o starts from zero
+                                    P[rb][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                        a[rb][p * KP + kk][NP == 1 ? 0 : PA[pp]],
+                                        b[kk % (PD + 1)][NP == 1 ? 0 : PB[pp]][c],
+                                        (p == 0 && kk == 0 && pp == 0) ? f32x4{0.f, 0.f, 0.f, 0.f} : P[rb][c], 0,
+                                        0, 0);
                     }
                     // keep that order through scheduling (left alone, the
                     // scheduler sinks every read next to its MFMAs to save
-                    // registers): the first two steps' reads, then per step
-                    // the reads two ahead and the step's MFMAs
-                    __builtin_amdgcn_sched_group_barrier(0x100, (KP < 2 ? KP : 2) * NCB, 0);
+                    // registers): the first PD steps' reads, then per step
+                    // the reads PD ahead and the step's MFMAs
+                    __builtin_amdgcn_sched_group_barrier(0x100, (KP < PD ? KP : PD) * NP * NCB, 0);
 #pragma unroll
                     for (int kk = 0; kk < KP; ++kk) {
-                        if (kk + 2 < KP) __builtin_amdgcn_sched_group_barrier(0x100, NCB, 0);
-                        __builtin_amdgcn_sched_group_barrier(0x008, NCB * RB, 0);
+                        if (kk + PD < KP) __builtin_amdgcn_sched_group_barrier(0x100, NP * NCB, 0);
+                        __builtin_amdgcn_sched_group_barrier(0x008, NPP * NCB * RB, 0);
                     }
                     if (p == NPART - 1) {  // W += T_o(x_q0) P at the accumulator rows 4g + v
                         const float *to = To + (og * gg.OG + oo) * ROWS_B + wave * ROWS_W + 4 * g;
@@ -543,8 +595,9 @@ static long long eval_K(int d, const int *n, int N4)
     return K;
 }
 
-// Geometry of the BF16 operand: outer mode, inner modes, chunking, slabs.
-static Bf16Geo bf16_geo(int d, const int *n, int &ksc)
+// Geometry of the BF16 operand (np pieces per coefficient): outer mode,
+// inner modes, chunking, slabs.
+static Bf16Geo bf16_geo(int d, const int *n, int &ksc, int np)
 {
     Bf16Geo gg;
     const int N4 = round4(n[d - 2]);
@@ -556,10 +609,13 @@ static Bf16Geo bf16_geo(int d, const int *n, int &ksc)
     const int steps = (gg.K2 + 31) / 32;
     // K-steps held in registers per chunk: fewest padded steps, counting two
     // steps of overhead (a W update) per chunk and outer value
+    // (the split form holds three pieces of each basis product: at most two
+    // K-steps in registers)
     const int cand[4] = {18, 6, 2, 1};
     int best = 1 << 30;
     ksc = 1;
     for (int c : cand) {
+        if (np > 1 && c > 2) continue;
         const int ch = (steps + c - 1) / c;
         const int cost = ch * (c + 2);
         if (cost < best) {
@@ -573,7 +629,7 @@ static Bf16Geo bf16_geo(int d, const int *n, int &ksc)
     // CU), at most 32 outer values with the padding (the kernel's T_o
     // table), fewest padded fragments counting four of overhead (a barrier)
     // per slab
-    const int kp = bf16_kp(ksc), f0 = kp * (n[d - 1] <= 16 ? 1 : 2);
+    const int kp = bf16_kp(ksc, np), f0 = kp * np * (n[d - 1] <= 16 ? 1 : 2);
     gg.OG = 1;
     if (kp == ksc) {
         best = 1 << 30;
@@ -595,10 +651,11 @@ size_t eval_ws_bytes(int d, const int *n, int precision)
     if (d < 2) return 0;
     const int N4 = round4(n[d - 2]);
     const int NC = n[d - 1] <= 16 ? 16 : 32;
-    if (precision == CG_BF16) {
+    if (precision == CG_BF16 || precision == CG_FP32_SPLIT) {
+        const int np = precision == CG_BF16 ? 1 : 3;
         int ksc;
-        const Bf16Geo gg = bf16_geo(d, n, ksc);
-        return (size_t)gg.n_og * gg.OG * gg.CH * ksc * (NC / 16) * 512 * 2 + 256;
+        const Bf16Geo gg = bf16_geo(d, n, ksc, np);
+        return (size_t)gg.n_og * gg.OG * gg.CH * ksc * np * (NC / 16) * 512 * 2 + 256;
     }
     const long long K = eval_K(d, n, N4);
     const size_t es = precision == CG_FP64 ? 8 : 4;
@@ -630,56 +687,70 @@ static hipError_t launch_eval_dn(const void *Bp, const double *x, TO *out, const
     return hipGetLastError();
 }
 
-template <int D, int N4, int NC, int KSC>
+template <int D, int N4, int NC, int KSC, int NP>
 static hipError_t launch_bf16_k(const double *coef, void *ws, const double *x, float *out, long long npts,
                                 const Bf16Geo &gg, hipStream_t s)
 {
     constexpr int ROWS_B = 128;
-    const long long total = (long long)gg.n_og * gg.OG * gg.CH * KSC * (NC / 16) * 512;
-    hipLaunchKernelGGL((k_pack_bf16<KSC, NC / 16>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, coef,
-                       (__bf16 *)ws, gg, N4);
+    const long long total = (long long)gg.n_og * gg.OG * gg.CH * KSC * NP * (NC / 16) * 512;
+    hipLaunchKernelGGL((k_pack_bf16<KSC, NC / 16, NP>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
+                       coef, (__bf16 *)ws, gg, N4);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     // dynamic LDS: the ring of three slabs, which also stages the W rows
-    const size_t ring = (size_t)3 * gg.OG * bf16_kp(KSC) * (NC / 16) * 1024;
+    const size_t ring = (size_t)3 * gg.OG * bf16_kp(KSC, NP) * NP * (NC / 16) * 1024;
     const size_t stage = (size_t)ROWS_B * (NC + 1) * sizeof(float);
     const size_t shm = ring > stage ? ring : stage;
     const unsigned blocks = (unsigned)((npts + ROWS_B - 1) / ROWS_B);
     if (shm > 48 * 1024) {
-        e = hipFuncSetAttribute((const void *)k_eval_bf16<D, N4, NC, KSC>,
+        e = hipFuncSetAttribute((const void *)k_eval_bf16<D, N4, NC, KSC, NP>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((k_eval_bf16<D, N4, NC, KSC>), dim3(blocks), dim3(256), shm, s, (const __bf16 *)ws, x, out,
-                       npts, gg);
+    hipLaunchKernelGGL((k_eval_bf16<D, N4, NC, KSC, NP>), dim3(blocks), dim3(256), shm, s, (const __bf16 *)ws, x,
+                       out, npts, gg);
     return hipGetLastError();
+}
+
+template <int D, int N4, int NP>
+static hipError_t launch_eval_bf16_dnp(const double *coef, void *ws, const double *x, float *out, long long npts,
+                                       const int *n, hipStream_t s)
+{
+    int ksc;
+    const Bf16Geo gg = bf16_geo(D, n, ksc, NP);
+    if constexpr (D < 4) {  // one K-step in all (bf16_geo)
+        if (n[D - 1] <= 16) return launch_bf16_k<D, N4, 16, 1, NP>(coef, ws, x, out, npts, gg, s);
+        return launch_bf16_k<D, N4, 32, 1, NP>(coef, ws, x, out, npts, gg, s);
+    } else if constexpr (NP > 1) {  // at most two K-steps per chunk (bf16_geo)
+        if (n[D - 1] <= 16)
+            return ksc == 2 ? launch_bf16_k<D, N4, 16, 2, NP>(coef, ws, x, out, npts, gg, s)
+                            : launch_bf16_k<D, N4, 16, 1, NP>(coef, ws, x, out, npts, gg, s);
+        return ksc == 2 ? launch_bf16_k<D, N4, 32, 2, NP>(coef, ws, x, out, npts, gg, s)
+                        : launch_bf16_k<D, N4, 32, 1, NP>(coef, ws, x, out, npts, gg, s);
+    } else {
+        if (n[D - 1] <= 16) {
+            switch (ksc) {
+                case 18: return launch_bf16_k<D, N4, 16, 18, NP>(coef, ws, x, out, npts, gg, s);
+                case 6: return launch_bf16_k<D, N4, 16, 6, NP>(coef, ws, x, out, npts, gg, s);
+                case 2: return launch_bf16_k<D, N4, 16, 2, NP>(coef, ws, x, out, npts, gg, s);
+                default: return launch_bf16_k<D, N4, 16, 1, NP>(coef, ws, x, out, npts, gg, s);
+            }
+        }
+        switch (ksc) {
+            case 18: return launch_bf16_k<D, N4, 32, 18, NP>(coef, ws, x, out, npts, gg, s);
+            case 6: return launch_bf16_k<D, N4, 32, 6, NP>(coef, ws, x, out, npts, gg, s);
+            case 2: return launch_bf16_k<D, N4, 32, 2, NP>(coef, ws, x, out, npts, gg, s);
+            default: return launch_bf16_k<D, N4, 32, 1, NP>(coef, ws, x, out, npts, gg, s);
+        }
+    }
 }
 
 template <int D, int N4>
 static hipError_t launch_eval_bf16_dn(const double *coef, void *ws, const double *x, float *out, long long npts,
-                                      const int *n, hipStream_t s)
+                                      const int *n, int np, hipStream_t s)
 {
-    int ksc;
-    const Bf16Geo gg = bf16_geo(D, n, ksc);
-    if constexpr (D < 4) {  // one K-step in all (bf16_geo)
-        if (n[D - 1] <= 16) return launch_bf16_k<D, N4, 16, 1>(coef, ws, x, out, npts, gg, s);
-        return launch_bf16_k<D, N4, 32, 1>(coef, ws, x, out, npts, gg, s);
-    } else {
-        if (n[D - 1] <= 16) {
-            switch (ksc) {
-                case 18: return launch_bf16_k<D, N4, 16, 18>(coef, ws, x, out, npts, gg, s);
-                case 6: return launch_bf16_k<D, N4, 16, 6>(coef, ws, x, out, npts, gg, s);
-                case 2: return launch_bf16_k<D, N4, 16, 2>(coef, ws, x, out, npts, gg, s);
-                default: return launch_bf16_k<D, N4, 16, 1>(coef, ws, x, out, npts, gg, s);
-            }
-        }
-        switch (ksc) {
-            case 18: return launch_bf16_k<D, N4, 32, 18>(coef, ws, x, out, npts, gg, s);
-            case 6: return launch_bf16_k<D, N4, 32, 6>(coef, ws, x, out, npts, gg, s);
-            case 2: return launch_bf16_k<D, N4, 32, 2>(coef, ws, x, out, npts, gg, s);
-            default: return launch_bf16_k<D, N4, 32, 1>(coef, ws, x, out, npts, gg, s);
-        }
-    }
+    return np == 1 ? launch_eval_bf16_dnp<D, N4, 1>(coef, ws, x, out, npts, n, s)
+                   : launch_eval_bf16_dnp<D, N4, 3>(coef, ws, x, out, npts, n, s);
 }
 
 #define CG_N4_SWITCH(N4v, CALL)                  \
@@ -709,10 +780,10 @@ static hipError_t launch_eval_d(const void *Bp, const double *x, void *out, cons
 
 template <int D>
 static hipError_t launch_eval_bf16_d(const double *coef, void *ws, const double *x, void *out, long long npts,
-                                     const int *n, hipStream_t s)
+                                     const int *n, int np, hipStream_t s)
 {
     const int N4 = round4(n[D - 2]);
-    CG_N4_SWITCH(N4, return (launch_eval_bf16_dn<D, N4c>(coef, ws, x, (float *)out, npts, n, s)))
+    CG_N4_SWITCH(N4, return (launch_eval_bf16_dn<D, N4c>(coef, ws, x, (float *)out, npts, n, np, s)))
     return hipErrorInvalidValue;
 }
 
@@ -731,11 +802,12 @@ hipError_t launch_eval(int d, const int *n, const double *coef, const double *x,
         return hipGetLastError();
     }
     if (ws_bytes < eval_ws_bytes(d, n, precision)) return hipErrorInvalidValue;
-    if (precision == CG_BF16) {
+    if (precision == CG_BF16 || precision == CG_FP32_SPLIT) {
+        const int np = precision == CG_BF16 ? 1 : 3;
         switch (d) {
-            case 2: return launch_eval_bf16_d<2>(coef, ws, x, out, npts, n, s);
-            case 3: return launch_eval_bf16_d<3>(coef, ws, x, out, npts, n, s);
-            case 4: return launch_eval_bf16_d<4>(coef, ws, x, out, npts, n, s);
+            case 2: return launch_eval_bf16_d<2>(coef, ws, x, out, npts, n, np, s);
+            case 3: return launch_eval_bf16_d<3>(coef, ws, x, out, npts, n, np, s);
+            case 4: return launch_eval_bf16_d<4>(coef, ws, x, out, npts, n, np, s);
         }
         return hipErrorInvalidValue;
     }

@@ -89,14 +89,27 @@ def test_eval_empty(cg):
     assert out.numel() == 0
 
 
-@pytest.mark.parametrize("prec,u_in", [("FP32", 2.0 ** -24), ("BF16", 2.0 ** -8)])
+def _eval_bound(prec, K, c):
+    """A-priori bound of the low-precision evaluations: inputs (basis
+    products, coefficients) rounded to the format (relative u_in each),
+    products exact or rounded once in binary32, binary32 accumulation
+    (gamma with u = 2^-24), last mode in binary64:
+        |err| <= (2 u_in + u_in^2 + e_split + gamma_{m K + 1}) * sum_k |c_k| |T_k(x)|
+    with |T_k(x)| <= 1 on [-1,1]^d.  FP32_SPLIT: u_in = 2^-24, both binary32
+    inputs split exactly into three bf16 pieces, the three dropped piece
+    products below e_split = 2^-23 + 2^-32 of the product (each piece is at
+    most 2^-8 of what it splits), m = 6 products per term."""
+    u32 = 2.0 ** -24
+    u_in, e_split, m = {"FP32": (u32, 0.0, 1), "BF16": (2.0 ** -8, 0.0, 1),
+                        "FP32_SPLIT": (u32, 2.0 ** -23 + 2.0 ** -32, 6)}[prec]
+    n = m * K + 1
+    gamma = n * u32 / (1 - n * u32)
+    return (2 * u_in + u_in * u_in + e_split + gamma) * np.sum(np.abs(c)) + 1e-30
+
+
+@pytest.mark.parametrize("prec", ["FP32", "BF16", "FP32_SPLIT"])
 @pytest.mark.parametrize("shape", [(16, 16), (12, 12, 12), (8, 8, 8, 8), (24, 24, 24, 24)])
-def test_eval_low_precision_within_bound(cg, orc, prec, u_in, shape):
-    # A-priori bound: inputs (basis products, coefficients) rounded to the
-    # format (relative u_in each), products exact or rounded once in binary32,
-    # K-term binary32 accumulation (gamma_K with u = 2^-24), last mode in
-    # binary64:  |err| <= (2 u_in + u_in^2 + gamma_{K+1}) * sum_k |c_k| |T_k(x)|
-    # with |T_k(x)| <= 1 on [-1,1]^d.
+def test_eval_low_precision_within_bound(cg, orc, prec, shape):
     say("eval", prec, shape)
     d = len(shape)
     N = shape[0]
@@ -105,33 +118,35 @@ def test_eval_low_precision_within_bound(cg, orc, prec, u_in, shape):
     out = cg.chebyshev_eval(dev(c), dev(x), getattr(cg, prec)).cpu().numpy().astype(np.float64)
     ref = orc.eval_points(c, x)
     K = int(np.prod(shape[:-1]))
-    u32 = 2.0 ** -24
-    gamma = (K + 1) * u32 / (1 - (K + 1) * u32)
-    bound = (2 * u_in + u_in * u_in + gamma) * np.sum(np.abs(c)) + 1e-30
+    bound = _eval_bound(prec, K, c)
     err = np.abs(out - ref)
     assert np.all(err <= bound), (err.max(), bound)
     say("  max err", err.max(), "bound", bound, "ratio", err.max() / bound)
 
 
+@pytest.mark.parametrize("prec", ["BF16", "FP32_SPLIT"])
 @pytest.mark.parametrize("shape,npts", [((5, 4), 999), ((17, 20), 130), ((6, 7, 9), 1000), ((3, 5, 4, 6), 1500),
                                         ((20, 13, 30, 7), 517), ((9, 31, 22, 17), 257), ((32, 32, 32, 32), 300)])
-def test_eval_bf16_ragged_within_bound(cg, orc, shape, npts):
-    """BF16 evaluation on uneven mode sizes (chunked inner index space,
-    padded last modes, ragged point counts) within the same a-priori bound."""
-    say("eval bf16", shape, npts)
+def test_eval_bf16_ragged_within_bound(cg, orc, prec, shape, npts):
+    """BF16 and split-bf16 evaluation on uneven mode sizes (chunked inner
+    index space, padded last modes, ragged point counts) within the same
+    a-priori bounds."""
+    say("eval", prec, shape, npts)
     d = len(shape)
     c = W.coef_tensor(d, max(shape), seed=19)[tuple(slice(0, s) for s in shape)].copy()
     x = W.query_points(d, npts, seed=19)
-    out = cg.chebyshev_eval(dev(c), dev(x), cg.BF16).cpu().numpy().astype(np.float64)
+    out = cg.chebyshev_eval(dev(c), dev(x), getattr(cg, prec)).cpu().numpy().astype(np.float64)
     ref = orc.eval_points(c, x)
     K = int(np.prod(shape[:-1]))
-    u32, u_in = 2.0 ** -24, 2.0 ** -8
-    gamma = (K + 1) * u32 / (1 - (K + 1) * u32)
-    bound = (2 * u_in + u_in * u_in + gamma) * np.sum(np.abs(c)) + 1e-30
+    bound = _eval_bound(prec, K, c)
     err = np.abs(out - ref)
     assert np.all(err <= bound), (err.max(), bound)
-    # and far from trivially so: the error is at the bf16 rounding level of the largest terms
-    assert err.max() <= 0.05 * bound or err.max() < 1e-2 * np.max(np.abs(ref))
+    if prec == "BF16":
+        # and far from trivially so: the error is at the bf16 rounding level of the largest terms
+        assert err.max() <= 0.05 * bound or err.max() < 1e-2 * np.max(np.abs(ref))
+    else:
+        # at the binary32 level: far below what bf16 operands give
+        assert err.max() <= 1e-3 * _eval_bound("BF16", K, c)
 
 
 # ---------------------------------------------------------------- game step
