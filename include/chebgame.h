@@ -329,8 +329,10 @@ int cg_profile(cg_game *game, int enable, double *kernel_ms, int64_t *launches);
 
 /* Tile shapes of the game's contraction kernel: rb row blocks of 16 nodes per
  * wave (1, 2 or 4) and ocb values of the outer modes per coefficient slab
- * (1 or 2; 1 when d = 2).  Defaults: rb = 2 (CG_FP32_CORR: 1, or 2 in the
- * split bfloat16 form), ocb = 2 (d = 2: 1).  Results do not depend on rb;
+ * (1 or 2; 1 when d = 2).  Defaults: rb = 2 when the game has rows for
+ * three waves per SIMD at that shape (d * N^d >= 98304), else 1 (always 1
+ * for d = 4 and for CG_FP32_CORR outside the split bfloat16 form), ocb = 2
+ * (d = 2: 1).  Results do not depend on rb;
  * ocb changes where the binary32 partial sums of CG_FP32_CORR enter FP64
  * (not in the split bfloat16 form, whose remainder enters FP64 once).
  * CG_EINVAL for other values. */

@@ -217,13 +217,22 @@ struct cg_game {
 };
 
 namespace cg {
-void default_tiles(int d, int N4, int precision, int &rb, int &ocb)
+void default_tiles(int d, int N4, long long NN, int precision, int &rb, int &ocb)
 {
-    // measured: d = 3, N = 32: FP64 fastest at (2, 2), FP32_CORR in the split
-    // bfloat16 form at (2, 2) (44.5 against 45.6 us at (1, 2)), binary32 form
-    // at (1, 2); d = 4, N = 24: FP64 at (1, 1), FP32_CORR at (1, 2)
+    // measured (contraction per launch): d = 3, N = 32: FP64 fastest at
+    // (2, 2), FP32_CORR in the split bfloat16 form at (2, 2) (44.5 against
+    // 45.6 us at (1, 2)); d = 3, N = 24: both at (1, 2) (FP64 39.6 against
+    // 51.9 us, split 25.1 against 31.0: two row blocks per wave leave 1.3
+    // waves per SIMD there); binary32 form at (1, 2); d = 4, N = 24: FP64 at
+    // (1, 1), FP32_CORR at (1, 2).  Two row blocks per wave once the game has
+    // rows for three such waves per SIMD.
+    const long long row_blocks = (long long)d * NN / 16;
+    const bool wide = row_blocks >= 2LL * 3 * 1024;
     const bool split = precision == CG_FP32_CORR && corr3_split16(d, N4);
-    rb = split ? 2 : ((precision == CG_FP32_CORR || d == 4) ? 1 : 2);
+    if (d == 4 || (precision == CG_FP32_CORR && !split))
+        rb = 1;
+    else
+        rb = wide ? 2 : 1;
     ocb = d >= 3 && !(d == 4 && precision != CG_FP32_CORR) ? 2 : 1;
 }
 const GameConst &game_consts(const cg_game *g) { return g->hc; }
@@ -450,7 +459,7 @@ int cg_init_game(const cg_game_desc *g, int precision, void *ws_dev, size_t ws_b
     b.ev_begin = b.ev_end = nullptr;
     b.tab = (const Inst *)(G->ws + L.tab);
     b.count = 1;
-    default_tiles(hc.d, hc.N4, precision, b.rb, b.ocb);
+    default_tiles(hc.d, hc.N4, hc.NN, precision, b.rb, b.ocb);
     InstPtrs &hi = G->inst;
     hi.gc = b.gc;
     hi.st = b.status;

@@ -287,7 +287,7 @@ int cg_batch_create(cg_game *const *games, int32_t count, void *ws_dev, size_t w
             Group G;
             G.hc = hc;
             G.precision = prec;
-            default_tiles(hc.d, hc.N4, prec, G.rb, G.ocb);
+            default_tiles(hc.d, hc.N4, hc.NN, prec, G.rb, G.ocb);
             G.tab_off = 0;
             B->groups.push_back(G);
             found = &B->groups.back();

@@ -205,7 +205,7 @@ const InstPtrs &game_inst(const cg_game *g);
 int game_precision(const cg_game *g);
 hipStream_t game_stream(const cg_game *g);
 // Default contraction tile shapes (row blocks per wave, outer values per slab).
-void default_tiles(int d, int N4, int precision, int &rb, int &ocb);
+void default_tiles(int d, int N4, long long NN, int precision, int &rb, int &ocb);
 // Records an error message for cg_last_error(); returns code.
 int set_error(int code, const char *msg);
 // CG_OK if the current device is a gfx950, else CG_EDEVICE with a message.
