@@ -840,32 +840,32 @@ void k_contract_corr3(
                 }
             } else {
 #pragma unroll
-            for (int ocl = 0; ocl < OCB; ++ocl) {
-                const int oc = sb * OCB + ocl;
-                const float *cb = lds + (sb & 1) * SLAB + ocl * N4 * LDB;
-                float bf[NT][NCB];
+                for (int ocl = 0; ocl < OCB; ++ocl) {
+                    const int oc = sb * OCB + ocl;
+                    const float *cb = lds + (sb & 1) * SLAB + ocl * N4 * LDB;
+                    float bf[NT][NCB];
 #pragma unroll
-                for (int t = 0; t < NT; ++t)
+                    for (int t = 0; t < NT; ++t)
 #pragma unroll
-                    for (int c = 0; c < NCB; ++c) bf[t][c] = cb[(4 * t + kq) * LDB + c * 16 + r16];
-                float fo[RB];
+                        for (int c = 0; c < NCB; ++c) bf[t][c] = cb[(4 * t + kq) * LDB + c * 16 + r16];
+                    float fo[RB];
 #pragma unroll
-                for (int rb = 0; rb < RB; ++rb) fo[rb] = dO[(wave * ROWS_W + rb * 16 + r16) * LDO + oc];
-                __builtin_amdgcn_sched_barrier(0);
+                    for (int rb = 0; rb < RB; ++rb) fo[rb] = dO[(wave * ROWS_W + rb * 16 + r16) * LDO + oc];
+                    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-                for (int t = 0; t < NT; ++t) {
+                    for (int t = 0; t < NT; ++t) {
 #pragma unroll
-                    for (int rb = 0; rb < RB; ++rb) {
-                        const float a = fo[rb] * Dn[rb][t];
+                        for (int rb = 0; rb < RB; ++rb) {
+                            const float a = fo[rb] * Dn[rb][t];
 #pragma unroll
-                        for (int c = 0; c < NCB; ++c) {
-                            const f32x4 cin = (q == 0 && ocl == 0 && t == 0) ? f32x4{0.f, 0.f, 0.f, 0.f}
-                                                                             : acc[rb][c];
-                            acc[rb][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bf[t][c], cin, 0, 0, 0);
+                            for (int c = 0; c < NCB; ++c) {
+                                const f32x4 cin = (q == 0 && ocl == 0 && t == 0) ? f32x4{0.f, 0.f, 0.f, 0.f}
+                                                                                 : acc[rb][c];
+                                acc[rb][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bf[t][c], cin, 0, 0, 0);
+                            }
                         }
                     }
                 }
-            }
             }
             if (more) {
                 if constexpr (SPLIT)
