@@ -756,7 +756,7 @@ def main():
                     help="also run a plain 1 GiB device copy (for scaling rocprof byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (instances or node blocks "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path (instances or node blocks "
               "would shard across GPUs with no or one all-gather per step; not built).", file=sys.stderr)
         sys.exit(2)
 

@@ -239,7 +239,7 @@ int cg_batch_destroy(cg_batch *batch);
 
 /* Learned warm start (an addition to the method: Section 2.2 leaves the
  * starting iterate V^[0] free; the network only chooses it, and the iteration
- * that follows is the plain method, which also judges the result).
+ * that follows is the plain method, which also decides the result).
  *
  * Network: 9 inputs (the six game parameters (A, beta, phi, c, kappa, rho) as
  * theta/nominal - 1, then the three normalised state coordinates x in

@@ -169,7 +169,7 @@ def _instances(lo, hi):
 def test_warm_start_gain_and_fallback(cg):
     """Train on solutions the method produces for 512 seeded d=3, N=8 games,
     then solve 12 held-out games to residual 1e-8 from the network's start and
-    from zero: the same answer (the plain method is the judge) in fewer
+    from zero: the same answer (the plain method decides it) in fewer
     iterations.  A corrupted network falls back and still converges."""
     tol = 1e-8
     train = _instances(0, 512)
