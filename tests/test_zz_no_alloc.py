@@ -41,7 +41,7 @@ def _inputs(shape, npts, seed):
             torch.as_tensor(x, dtype=torch.float64, device="cuda"))
 
 
-@pytest.mark.parametrize("precision", [0, 1, 2])
+@pytest.mark.parametrize("precision", [0, 1, 2, 4])  # FP64, FP32, BF16, FP32_SPLIT
 def test_noalloc_matches_workspace_entry(cg, precision):
     big = _inputs((32, 32, 32, 32), 3000, seed=41)
     small = _inputs((13, 7, 21), 517, seed=42)
