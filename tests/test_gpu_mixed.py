@@ -135,10 +135,10 @@ def _basis(n, x):
     return V, D
 
 
-@pytest.mark.parametrize("N", [12, 24])
+@pytest.mark.parametrize("N", [12, 24, 32])
 def test_one_step_within_a_priori_bound(cg, orc, N):
     """One mixed step from a smooth state (N = 12: the oracle's iterate after
-    12 steps; N = 24: a seeded smooth state) against the oracle's step, per
+    12 steps; N = 24, 32: a seeded smooth state) against the oracle's step, per
     sampled (player, node), within
 
         |dV| <= delta * sum_{k_i} max_line |T_{k_i}| * |dw_{k_i}|,
@@ -157,7 +157,7 @@ def test_one_step_within_a_priori_bound(cg, orc, N):
     and the coefficients come from numpy and the oracle.  The FP64 rest of
     the step adds its own budget, 1e-13 max|V|.
 
-    From N4 = 20 on (N = 24 here) the D_a D_c product runs in the split
+    From N4 = 20 on (N = 24, 32 here) the D_a D_c product runs in the split
     bfloat16 form: D_c and the coefficient, each rounded to binary32 once,
     are split exactly into three bfloat16 pieces, the three dropped piece
     products are below 2 u |D_c c| (each piece is at most 2^-8 of what it
